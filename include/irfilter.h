@@ -1,0 +1,133 @@
+/*
+ * irfilter.h -- C ABI of the MI355X FNR impulse filter (libirfilter.so).
+ *
+ * The method is the Fast Noise Reduction (FNR) filter of Gupta, Beg and
+ * Niranjan, "A Novel Approach to Fast Image Filtering Algorithm of Infrared
+ * Images based on Intro Sort Algorithm":
+ *   - S_xy is the k x k window around pixel (x, y), centre included; x is the
+ *     column and y the row (Section 3.3);
+ *   - a pixel is noisy when its grey level equals the minimum or the maximum of
+ *     S_xy (Eq. 3a/3b, Step 2 of Section 3.3); ties count;
+ *   - a noisy pixel is replaced by the median of S_xy, signal pixels keep their
+ *     value (Section 3.4);
+ *   - the whole frame may be filtered more than once (Section 4, Fig. 5-6).
+ * Readings where the paper is silent: windows at the border repeat the edge
+ * pixels (replicate); every pass reads an unchanged copy of its input; the
+ * window side k is odd and the median is element (k*k-1)/2 of the sorted
+ * window; 16-bit pixels are compared as full 16-bit values.
+ *
+ * Frames are single-channel, row-major, uint8 or uint16.  A "pitch" is the
+ * byte distance between the starts of two rows (>= width * bytes per pixel);
+ * only the first width * bytes bytes of each row are read or written.
+ *
+ * Memory and ownership: every frame, mask, scratch and counter pointer is a
+ * DEVICE pointer owned by the caller (e.g. a torch CUDA tensor's data_ptr()).
+ * The per-frame entry points allocate nothing.  Only an irf_plan owns device
+ * memory (its descriptor table), released by ir_filter_plan_destroy.
+ *
+ * Execution: calls enqueue work on `stream` (NULL = the default stream) and
+ * return without waiting.  The status reports argument validation, which runs
+ * on the host before any HIP call, and launch errors.  No exception or abort
+ * crosses this interface.  Calls on different streams may run concurrently.
+ * Outputs must not overlap inputs (IRF_ERR_ALIAS): a tile's window reads would
+ * race another tile's stores.
+ *
+ * Fast path: when every base address, pitch and frame stride is a multiple of
+ * 16 bytes, interior tiles use 16-byte vector loads and stores; other layouts
+ * are handled correctly with narrower accesses.
+ */
+#ifndef IRFILTER_H
+#define IRFILTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { IRF_U8 = 1, IRF_U16 = 2 } irf_dtype;
+
+typedef enum {
+    IRF_OK = 0,
+    IRF_ERR_NULL = -1,    /* a required pointer is NULL */
+    IRF_ERR_DIMS = -2,    /* width/height outside 1..IRF_MAX_DIM, or frame count < 1 */
+    IRF_ERR_PITCH = -3,   /* a pitch is smaller than one row, or a stride smaller than one frame */
+    IRF_ERR_DTYPE = -4,   /* pixel type is not IRF_U8 or IRF_U16 */
+    IRF_ERR_WINDOW = -5,  /* window is not odd or outside 3..IRF_MAX_WINDOW */
+    IRF_ERR_PASSES = -6,  /* passes outside 1..IRF_MAX_PASSES, or scratch missing for passes >= 2 */
+    IRF_ERR_ALIAS = -7,   /* an output overlaps an input or another output */
+    IRF_ERR_HIP = -8,     /* a HIP call failed (the HIP error is cleared) */
+    IRF_ERR_NOMEM = -9,   /* device or host allocation failed (plans only) */
+    IRF_ERR_CAPACITY = -10 /* a batch exceeds the plan's capacity */
+} irf_status;
+
+#define IRF_MAX_DIM 32768
+#define IRF_MAX_WINDOW 15
+#define IRF_MAX_PASSES 16
+
+/*
+ * ir_filter_detect -- noise detection (Section 3.3, Eq. 3a/3b and Step 2).
+ *   src, src_pitch       input frame (device, read only)
+ *   mask, mask_pitch     output (device): mask[y*mask_pitch + x] = 1 if pixel (x, y)
+ *                        equals its window's min or max, else 0; mask_pitch >= width
+ *   width, height        1..IRF_MAX_DIM
+ *   dtype, window        pixel type; odd window side 3..IRF_MAX_WINDOW
+ *   flagged_count        nullable device uint64: set to the number of noisy pixels
+ *                        (zeroed on the stream, then accumulated)
+ */
+irf_status ir_filter_detect(const void *src, size_t src_pitch, uint8_t *mask, size_t mask_pitch,
+                            int width, int height, irf_dtype dtype, int window,
+                            uint64_t *flagged_count, hipStream_t stream);
+
+/*
+ * ir_filter_median -- median replacement (Section 3.4).
+ *   mask (nullable)      where mask[y*mask_pitch + x] != 0 the pixel takes its window
+ *                        median; other pixels are copied.  mask == NULL replaces
+ *                        every pixel: the standard median filter of Section 2.
+ *   dst, dst_pitch       output frame (device), same type and size as src
+ */
+irf_status ir_filter_median(const void *src, size_t src_pitch, const uint8_t *mask,
+                            size_t mask_pitch, void *dst, size_t dst_pitch, int width, int height,
+                            irf_dtype dtype, int window, hipStream_t stream);
+
+/*
+ * ir_filter_run -- the whole FNR filter, `passes` times (Sections 3.3-3.4, 4).
+ *   Detection and median replacement are fused in one kernel per pass.
+ *   passes               1..IRF_MAX_PASSES; pass i reads the output of pass i-1
+ *   scratch, scratch_pitch  device frame of the same size and type, required when
+ *                        passes >= 2 (intermediate passes alternate between it and
+ *                        dst so that the last one lands in dst); ignored otherwise
+ *   flagged_count        nullable device array of `passes` uint64: noisy pixels found
+ *                        by each pass (zeroed on the stream, then accumulated)
+ */
+irf_status ir_filter_run(const void *src, size_t src_pitch, void *dst, size_t dst_pitch, int width,
+                         int height, irf_dtype dtype, int window, int passes, void *scratch,
+                         size_t scratch_pitch, uint64_t *flagged_count, hipStream_t stream);
+
+/*
+ * ir_filter_run_frames -- ir_filter_run over a stack of `nframes` frames of the
+ * same size, one launch per pass.  Frame i starts at src + i*src_stride (bytes),
+ * dst + i*dst_stride, scratch + i*scratch_stride.  Frames are filtered
+ * independently; flagged_count[p] (nullable, `passes` entries) receives the
+ * noisy pixels of pass p summed over all frames.
+ */
+irf_status ir_filter_run_frames(const void *src, size_t src_pitch, size_t src_stride, void *dst,
+                                size_t dst_pitch, size_t dst_stride, int width, int height,
+                                int nframes, irf_dtype dtype, int window, int passes, void *scratch,
+                                size_t scratch_pitch, size_t scratch_stride,
+                                uint64_t *flagged_count, hipStream_t stream);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *ir_filter_status_string(irf_status status);
+
+/* Library ABI version: (major << 16) | minor. */
+int ir_filter_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IRFILTER_H */

@@ -1,0 +1,276 @@
+// irfilter.hip -- host runtime and C ABI of the FNR filter (see include/irfilter.h).
+//
+// Validation runs on the host before any HIP call, so argument errors are
+// reported without touching the device.  Launches go to the caller's stream;
+// nothing here allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "../../include/irfilter.h"
+#include "fnr_device.hpp"
+
+namespace irf {
+namespace {
+
+constexpr int kVersion = (1 << 16) | 0;
+
+int bytes_of(irf_dtype d) { return d == IRF_U8 ? 1 : (d == IRF_U16 ? 2 : 0); }
+
+// One frame stack as seen by validation: [base, base + extent) must not overlap
+// another output or input.
+struct Span {
+    uintptr_t lo, hi;
+};
+
+Span span_of(const void *p, size_t pitch, size_t stride, int width, int height, int nframes,
+             int bytes) {
+    uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    uint64_t ext = (uint64_t)stride * (uint64_t)(nframes - 1) + (uint64_t)pitch * (uint64_t)(height - 1) +
+                   (uint64_t)width * (uint64_t)bytes;
+    return {lo, lo + (uintptr_t)ext};
+}
+
+bool overlap(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
+
+bool is16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool is16(size_t v) { return (v & 15u) == 0; }
+
+irf_status check_common(int width, int height, int nframes, irf_dtype dtype, int window) {
+    if (width < 1 || height < 1 || width > IRF_MAX_DIM || height > IRF_MAX_DIM || nframes < 1)
+        return IRF_ERR_DIMS;
+    if (bytes_of(dtype) == 0) return IRF_ERR_DTYPE;
+    if (window < 3 || window > IRF_MAX_WINDOW || (window & 1) == 0) return IRF_ERR_WINDOW;
+    return IRF_OK;
+}
+
+irf_status check_layout(size_t pitch, size_t stride, int width, int height, int nframes, int bytes) {
+    if (pitch < (size_t)width * (size_t)bytes) return IRF_ERR_PITCH;
+    if (nframes > 1 && stride < pitch * (size_t)height) return IRF_ERR_PITCH;
+    return IRF_OK;
+}
+
+int tile_rows(int window) {
+    (void)window;
+    return kStrips * Geometry<3>::R;  // every window uses the same tile height
+}
+
+template <typename T, int K, int MODE>
+void launch_t(const StackArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((fnr_stack_kernel<T, K, MODE>), dim3(a.total_tiles), dim3(kThreads), 0, s, a);
+}
+
+template <typename T, int MODE>
+bool launch_k(int window, const StackArgs &a, hipStream_t s) {
+    switch (window) {
+        case 3: launch_t<T, 3, MODE>(a, s); return true;
+        case 5: launch_t<T, 5, MODE>(a, s); return true;
+        case 7: launch_t<T, 7, MODE>(a, s); return true;
+        case 9: launch_t<T, 9, MODE>(a, s); return true;
+        case 11: launch_t<T, 11, MODE>(a, s); return true;
+        case 13: launch_t<T, 13, MODE>(a, s); return true;
+        case 15: launch_t<T, 15, MODE>(a, s); return true;
+        default: return false;
+    }
+}
+
+template <int MODE>
+irf_status launch(irf_dtype dtype, int window, int nframes, StackArgs a, hipStream_t s) {
+    const int th = tile_rows(window);
+    a.tiles_x = (a.width + kTileW - 1) / kTileW;
+    const int tiles_y = (a.height + th - 1) / th;
+    const uint64_t per_frame = (uint64_t)a.tiles_x * (uint64_t)tiles_y;
+    const uint64_t total = per_frame * (uint64_t)nframes;
+    if (total > 0x7fffffffull) return IRF_ERR_DIMS;
+    a.tiles_per_frame = (int)per_frame;
+    a.total_tiles = (int)total;
+    (void)hipGetLastError();
+    bool ok = dtype == IRF_U8 ? launch_k<uint8_t, MODE>(window, a, s)
+                              : launch_k<uint16_t, MODE>(window, a, s);
+    if (!ok) return IRF_ERR_WINDOW;
+    if (hipGetLastError() != hipSuccess) return IRF_ERR_HIP;
+    return IRF_OK;
+}
+
+irf_status zero_counts(uint64_t *p, int n, hipStream_t s) {
+    if (!p) return IRF_OK;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 63) / 64), dim3(64), 0, s,
+                       reinterpret_cast<unsigned long long *>(p), n);
+    return hipGetLastError() == hipSuccess ? IRF_OK : IRF_ERR_HIP;
+}
+
+irf_status run_frames(const void *src, size_t src_pitch, size_t src_stride, void *dst,
+                      size_t dst_pitch, size_t dst_stride, int width, int height, int nframes,
+                      irf_dtype dtype, int window, int passes, void *scratch, size_t scratch_pitch,
+                      size_t scratch_stride, uint64_t *counts, hipStream_t stream) {
+    if (!src || !dst) return IRF_ERR_NULL;
+    irf_status st = check_common(width, height, nframes, dtype, window);
+    if (st) return st;
+    if (passes < 1 || passes > IRF_MAX_PASSES) return IRF_ERR_PASSES;
+    if (passes >= 2 && !scratch) return IRF_ERR_PASSES;
+    const int b = bytes_of(dtype);
+    if ((st = check_layout(src_pitch, src_stride, width, height, nframes, b))) return st;
+    if ((st = check_layout(dst_pitch, dst_stride, width, height, nframes, b))) return st;
+    const Span ss = span_of(src, src_pitch, src_stride, width, height, nframes, b);
+    const Span ds = span_of(dst, dst_pitch, dst_stride, width, height, nframes, b);
+    if (overlap(ss, ds)) return IRF_ERR_ALIAS;
+    if (passes >= 2) {
+        if ((st = check_layout(scratch_pitch, scratch_stride, width, height, nframes, b))) return st;
+        const Span xs = span_of(scratch, scratch_pitch, scratch_stride, width, height, nframes, b);
+        if (overlap(xs, ss) || overlap(xs, ds)) return IRF_ERR_ALIAS;
+    }
+    if (counts) {
+        const Span cs = {reinterpret_cast<uintptr_t>(counts),
+                         reinterpret_cast<uintptr_t>(counts) + sizeof(uint64_t) * (size_t)passes};
+        if (overlap(cs, ss) || overlap(cs, ds)) return IRF_ERR_ALIAS;
+    }
+    if ((st = zero_counts(counts, passes, stream))) return st;
+    // Pass i reads A_{i-1} and writes A_i; A_0 = src, A_passes = dst, and the
+    // intermediate frames alternate so that an even distance from the end is dst.
+    const void *in = src;
+    size_t in_pitch = src_pitch, in_stride = src_stride;
+    for (int p = 1; p <= passes; ++p) {
+        const bool to_dst = ((passes - p) & 1) == 0;
+        void *out = to_dst ? dst : scratch;
+        const size_t out_pitch = to_dst ? dst_pitch : scratch_pitch;
+        const size_t out_stride = to_dst ? dst_stride : scratch_stride;
+        StackArgs a = {};
+        a.src = static_cast<const uint8_t *>(in);
+        a.dst = static_cast<uint8_t *>(out);
+        a.src_pitch = in_pitch;
+        a.dst_pitch = out_pitch;
+        a.src_stride = in_stride;
+        a.dst_stride = out_stride;
+        a.width = width;
+        a.height = height;
+        a.aligned = is16(in) && is16(out) && is16(in_pitch) && is16(out_pitch) &&
+                    (nframes == 1 || (is16(in_stride) && is16(out_stride)));
+        a.count = counts ? reinterpret_cast<unsigned long long *>(counts + (p - 1)) : nullptr;
+        if ((st = launch<MODE_FNR>(dtype, window, nframes, a, stream))) return st;
+        in = out;
+        in_pitch = out_pitch;
+        in_stride = out_stride;
+    }
+    return IRF_OK;
+}
+
+}  // namespace
+}  // namespace irf
+
+using namespace irf;
+
+extern "C" {
+
+irf_status ir_filter_detect(const void *src, size_t src_pitch, uint8_t *mask, size_t mask_pitch,
+                            int width, int height, irf_dtype dtype, int window,
+                            uint64_t *flagged_count, hipStream_t stream) {
+    try {
+        if (!src || !mask) return IRF_ERR_NULL;
+        irf_status st = check_common(width, height, 1, dtype, window);
+        if (st) return st;
+        const int b = bytes_of(dtype);
+        if ((st = check_layout(src_pitch, 0, width, height, 1, b))) return st;
+        if ((st = check_layout(mask_pitch, 0, width, height, 1, 1))) return st;
+        const Span ss = span_of(src, src_pitch, 0, width, height, 1, b);
+        const Span ms = span_of(mask, mask_pitch, 0, width, height, 1, 1);
+        if (overlap(ss, ms)) return IRF_ERR_ALIAS;
+        if (flagged_count) {
+            const Span cs = {reinterpret_cast<uintptr_t>(flagged_count),
+                             reinterpret_cast<uintptr_t>(flagged_count) + sizeof(uint64_t)};
+            if (overlap(cs, ss) || overlap(cs, ms)) return IRF_ERR_ALIAS;
+        }
+        if ((st = zero_counts(flagged_count, 1, stream))) return st;
+        StackArgs a = {};
+        a.src = static_cast<const uint8_t *>(src);
+        a.mask_out = mask;
+        a.src_pitch = src_pitch;
+        a.mask_pitch = mask_pitch;
+        a.width = width;
+        a.height = height;
+        a.aligned = is16(src) && is16(src_pitch) && is16(mask) && is16(mask_pitch);
+        a.count = reinterpret_cast<unsigned long long *>(flagged_count);
+        return launch<MODE_DETECT>(dtype, window, 1, a, stream);
+    } catch (...) {
+        return IRF_ERR_HIP;
+    }
+}
+
+irf_status ir_filter_median(const void *src, size_t src_pitch, const uint8_t *mask,
+                            size_t mask_pitch, void *dst, size_t dst_pitch, int width, int height,
+                            irf_dtype dtype, int window, hipStream_t stream) {
+    try {
+        if (!src || !dst) return IRF_ERR_NULL;
+        irf_status st = check_common(width, height, 1, dtype, window);
+        if (st) return st;
+        const int b = bytes_of(dtype);
+        if ((st = check_layout(src_pitch, 0, width, height, 1, b))) return st;
+        if ((st = check_layout(dst_pitch, 0, width, height, 1, b))) return st;
+        if (mask && (st = check_layout(mask_pitch, 0, width, height, 1, 1))) return st;
+        const Span ss = span_of(src, src_pitch, 0, width, height, 1, b);
+        const Span ds = span_of(dst, dst_pitch, 0, width, height, 1, b);
+        if (overlap(ss, ds)) return IRF_ERR_ALIAS;
+        if (mask && overlap(span_of(mask, mask_pitch, 0, width, height, 1, 1), ds)) return IRF_ERR_ALIAS;
+        StackArgs a = {};
+        a.src = static_cast<const uint8_t *>(src);
+        a.dst = static_cast<uint8_t *>(dst);
+        a.mask_in = mask;
+        a.src_pitch = src_pitch;
+        a.dst_pitch = dst_pitch;
+        a.mask_pitch = mask_pitch;
+        a.width = width;
+        a.height = height;
+        a.aligned = is16(src) && is16(src_pitch) && is16(dst) && is16(dst_pitch) &&
+                    (!mask || (is16(mask) && is16(mask_pitch)));
+        return mask ? launch<MODE_MEDIAN_MASK>(dtype, window, 1, a, stream)
+                    : launch<MODE_MEDIAN_ALL>(dtype, window, 1, a, stream);
+    } catch (...) {
+        return IRF_ERR_HIP;
+    }
+}
+
+irf_status ir_filter_run(const void *src, size_t src_pitch, void *dst, size_t dst_pitch, int width,
+                         int height, irf_dtype dtype, int window, int passes, void *scratch,
+                         size_t scratch_pitch, uint64_t *flagged_count, hipStream_t stream) {
+    try {
+        return run_frames(src, src_pitch, 0, dst, dst_pitch, 0, width, height, 1, dtype, window,
+                          passes, scratch, scratch_pitch, 0, flagged_count, stream);
+    } catch (...) {
+        return IRF_ERR_HIP;
+    }
+}
+
+irf_status ir_filter_run_frames(const void *src, size_t src_pitch, size_t src_stride, void *dst,
+                                size_t dst_pitch, size_t dst_stride, int width, int height,
+                                int nframes, irf_dtype dtype, int window, int passes, void *scratch,
+                                size_t scratch_pitch, size_t scratch_stride,
+                                uint64_t *flagged_count, hipStream_t stream) {
+    try {
+        return run_frames(src, src_pitch, src_stride, dst, dst_pitch, dst_stride, width, height,
+                          nframes, dtype, window, passes, scratch, scratch_pitch, scratch_stride,
+                          flagged_count, stream);
+    } catch (...) {
+        return IRF_ERR_HIP;
+    }
+}
+
+const char *ir_filter_status_string(irf_status s) {
+    switch (s) {
+        case IRF_OK: return "ok";
+        case IRF_ERR_NULL: return "null pointer";
+        case IRF_ERR_DIMS: return "invalid dimensions";
+        case IRF_ERR_PITCH: return "pitch or stride too small";
+        case IRF_ERR_DTYPE: return "unsupported pixel type";
+        case IRF_ERR_WINDOW: return "window must be odd and within 3..15";
+        case IRF_ERR_PASSES: return "invalid pass count or missing scratch";
+        case IRF_ERR_ALIAS: return "output overlaps an input";
+        case IRF_ERR_HIP: return "HIP error";
+        case IRF_ERR_NOMEM: return "out of memory";
+        case IRF_ERR_CAPACITY: return "batch exceeds plan capacity";
+    }
+    return "unknown status";
+}
+
+int ir_filter_version(void) { return kVersion; }
+
+}  // extern "C"

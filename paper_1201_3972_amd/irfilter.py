@@ -1,0 +1,183 @@
+"""ctypes binding of ``libirfilter.so`` (declared in ``include/irfilter.h``).
+
+Argument marshalling only: every step of the filter runs in the library's HIP
+kernels.  Functions take torch CUDA tensors (torch provides device memory and
+streams) and pass their data pointers, row pitches and the current stream to the
+C entry points of the same name.  A 2-D tensor is one frame ``[H, W]`` whose row
+pitch is ``stride(0) * element_size()``; a 3-D tensor ``[N, H, W]`` is a stack.
+Pixel types: ``torch.uint8`` and ``torch.uint16`` (``torch.int16`` is accepted
+as raw 16-bit storage and filtered as unsigned).
+
+If the shared library has not been built, every call raises
+``LibraryNotBuilt``: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libirfilter.so")
+
+IRF_U8 = 1
+IRF_U16 = 2
+
+STATUS = {
+    0: "IRF_OK", -1: "IRF_ERR_NULL", -2: "IRF_ERR_DIMS", -3: "IRF_ERR_PITCH", -4: "IRF_ERR_DTYPE",
+    -5: "IRF_ERR_WINDOW", -6: "IRF_ERR_PASSES", -7: "IRF_ERR_ALIAS", -8: "IRF_ERR_HIP",
+    -9: "IRF_ERR_NOMEM", -10: "IRF_ERR_CAPACITY",
+}
+
+# name -> (restype, argtypes); mirrors include/irfilter.h
+_vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+SIGNATURES = {
+    "ir_filter_detect": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _vp, _vp]),
+    "ir_filter_median": (_i32, [_vp, _sz, _vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _vp]),
+    "ir_filter_run": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp]),
+    "ir_filter_run_frames": (_i32, [_vp, _sz, _sz, _vp, _sz, _sz, _i32, _i32, _i32, _i32, _i32, _i32,
+                                    _vp, _sz, _sz, _vp, _vp]),
+    "ir_filter_status_string": (ctypes.c_char_p, [_i32]),
+    "ir_filter_version": (_i32, []),
+}
+
+
+class LibraryNotBuilt(ImportError):
+    pass
+
+
+class IrfError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        self.status = status
+        super().__init__(f"{fn} failed: {STATUS.get(status, status)} ({status_string(status)})")
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load the library (once) and declare its signatures."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise LibraryNotBuilt(f"{p} is missing: run paper_1201_3972_amd.build.build() "
+                              "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return load().ir_filter_status_string(status).decode()
+    except LibraryNotBuilt:
+        return STATUS.get(status, "unknown")
+
+
+def _check(fn: str, status: int) -> None:
+    if status != 0:
+        raise IrfError(fn, status)
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.uint8:
+        return IRF_U8
+    if t.dtype in (torch.uint16, torch.int16):
+        return IRF_U16
+    raise TypeError(f"unsupported pixel type {t.dtype}; use uint8 or uint16")
+
+
+def _frame(t, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D [H, W]")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} rows must be contiguous")
+    return t.data_ptr(), t.stride(0) * t.element_size()
+
+
+def _stack(t, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dim() != 3:
+        raise ValueError(f"{name} must be 3-D [N, H, W]")
+    if t.stride(2) != 1:
+        raise ValueError(f"{name} rows must be contiguous")
+    es = t.element_size()
+    return t.data_ptr(), t.stride(1) * es, t.stride(0) * es
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _same(a, b, what: str):
+    if a.shape != b.shape or _dtype_code(a) != _dtype_code(b):
+        raise ValueError(f"{what} must match the source shape and pixel type")
+
+
+def ir_filter_detect(src, mask, window: int, flagged_count=None, stream=None) -> None:
+    """Noise mask (uint8, 1 = noisy) of ``src``; optional uint64 count tensor (1 element)."""
+    sp, spitch = _frame(src, "src")
+    mp, mpitch = _frame(mask, "mask")
+    H, W = src.shape
+    if tuple(mask.shape) != (H, W):
+        raise ValueError("mask must have the source shape")
+    cp = None if flagged_count is None else flagged_count.data_ptr()
+    _check("ir_filter_detect", load().ir_filter_detect(sp, spitch, mp, mpitch, W, H, _dtype_code(src),
+                                                       window, cp, _stream(stream)))
+
+
+def ir_filter_median(src, dst, window: int, mask=None, stream=None) -> None:
+    """Window median where ``mask`` != 0 (every pixel when ``mask`` is None)."""
+    _same(src, dst, "dst")
+    sp, spitch = _frame(src, "src")
+    dp, dpitch = _frame(dst, "dst")
+    mp, mpitch = (None, 0) if mask is None else _frame(mask, "mask")
+    H, W = src.shape
+    _check("ir_filter_median", load().ir_filter_median(sp, spitch, mp, mpitch, dp, dpitch, W, H,
+                                                       _dtype_code(src), window, _stream(stream)))
+
+
+def ir_filter_run(src, dst, window: int, passes: int = 1, scratch=None, flagged_count=None,
+                  stream=None) -> None:
+    """FNR ``passes`` times; ``flagged_count`` (uint64/int64, ``passes`` elements) is optional."""
+    _same(src, dst, "dst")
+    sp, spitch = _frame(src, "src")
+    dp, dpitch = _frame(dst, "dst")
+    xp, xpitch = (None, 0) if scratch is None else _frame(scratch, "scratch")
+    H, W = src.shape
+    cp = None if flagged_count is None else flagged_count.data_ptr()
+    _check("ir_filter_run", load().ir_filter_run(sp, spitch, dp, dpitch, W, H, _dtype_code(src), window,
+                                                 passes, xp, xpitch, cp, _stream(stream)))
+
+
+def ir_filter_run_frames(src, dst, window: int, passes: int = 1, scratch=None, flagged_count=None,
+                         stream=None) -> None:
+    """FNR over a stack ``[N, H, W]`` in one launch per pass."""
+    _same(src, dst, "dst")
+    sp, spitch, sstride = _stack(src, "src")
+    dp, dpitch, dstride = _stack(dst, "dst")
+    xp, xpitch, xstride = (None, 0, 0) if scratch is None else _stack(scratch, "scratch")
+    N, H, W = src.shape
+    cp = None if flagged_count is None else flagged_count.data_ptr()
+    _check("ir_filter_run_frames",
+           load().ir_filter_run_frames(sp, spitch, sstride, dp, dpitch, dstride, W, H, N, _dtype_code(src),
+                                       window, passes, xp, xpitch, xstride, cp, _stream(stream)))
+
+
+def version() -> int:
+    return load().ir_filter_version()

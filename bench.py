@@ -77,6 +77,8 @@ def main() -> int:
     ap.add_argument("--pool", type=int, default=4, help="distinct frames per noise density")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-frame", action="store_true", help="skip the per-frame launch baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -93,6 +95,16 @@ def main() -> int:
         return 2
     irfilter.load()
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device=dev)
+        b = torch.empty(n, dtype=torch.uint8, device=dev)
+        a.fill_(1)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return 0
     windows = list(synth.C2_WINDOWS)
     N = args.frames
 

@@ -9,18 +9,21 @@
 //     (Section 3.4); the frame may be filtered several times (Section 4).
 // Border windows replicate the edge pixels; each pass reads an unchanged input.
 //
-// One workgroup of 256 threads filters one tile of kTileW x (8*R) output
-// pixels.  The tile and an r-pixel halo (rounded out to 8 columns) are staged in
-// LDS as 16-bit values, whatever the pixel type.  The steps:
+// A persistent workgroup of 256 threads walks a range of tiles of kTileW x (8*R)
+// output pixels.  Each tile and an r-pixel halo (rounded out to 8 columns) are
+// staged in LDS as 16-bit values, whatever the pixel type.  The steps:
 //   1. load:    coalesced 8-pixel chunks, rows and columns clamped at the border;
+//               the next tile's loads are issued into registers before the
+//               current tile is processed, so HBM reads overlap the compute;
 //   2. detect:  every thread owns 4 columns x R rows; window min and max are
 //               separable: per input row a packed-u16 horizontal min/max over k
 //               columns (two pixels per VGPR), then a van Herk / Gil-Werman
 //               sliding min/max down the R+k-1 rows;
 //   3. compact: flagged pixels of the tile go to an LDS list (wave prefix scan);
 //   4. select:  each lane takes two list entries and computes both medians in
-//               packed u16 registers: k <= 7 by forgetful selection over a sorted
-//               working set, k >= 9 by a bisection on grey level that counts the
+//               packed u16 registers: k <= 9 by forgetful selection over sorted
+//               blocks merged into a sorted run whose provably-non-median ends
+//               are dropped, k >= 11 by a bisection on grey level that counts the
 //               window values at or below the probe (bit-by-bit value search);
 //   5. store:   results replace the flagged pixels in LDS, then the tile is
 //               written out with vector stores.
@@ -40,8 +43,11 @@ constexpr int kTileW = 128;                  // output columns per tile
 constexpr int kThreadsX = kTileW / 4;        // 32 threads across, 4 columns each
 constexpr int kStrips = kThreads / kThreadsX;  // 8 strips of R rows
 constexpr int kHalo = 8;                     // LDS columns kept left and right of the tile
-constexpr int kLdsW = kTileW + 2 * kHalo;    // 144 16-bit values per LDS row
+constexpr int kLdsW = kTileW + 2 * kHalo;    // 144 16-bit values staged per LDS row
 constexpr int kChunks = kLdsW / 8;           // 8-pixel load chunks per LDS row
+// LDS row pitch in 16-bit values: 76 dwords, so rows 8 apart (the two 32-lane
+// halves of a wave during detection) fall on opposite halves of the 64 banks.
+constexpr int kLdsPitch = kLdsW + 8;
 constexpr int kMaxWindow = 15;
 
 enum Mode : int {
@@ -64,6 +70,9 @@ struct StackArgs {
     int total_tiles;
     int aligned;  // every base address and pitch is a multiple of 16 bytes
     unsigned long long *count;  // nullable: += flagged pixels
+    // 0x00010001, passed in so the compiler keeps the packed min with it as one
+    // v_pk_min_u16 instead of expanding it into per-half compares and selects
+    uint32_t pk_one;
 };
 
 template <int K>
@@ -73,6 +82,8 @@ struct Geometry {
     static constexpr int TH = kStrips * R;
     static constexpr int rows = TH + 2 * r;  // LDS rows
     static constexpr int tile_px = kTileW * TH;
+    static constexpr int chunks = rows * kChunks;                      // 8-pixel chunks
+    static constexpr int per_thread = (chunks + kThreads - 1) / kThreads;
     static_assert(K >= 3 && K <= kMaxWindow && (K & 1), "odd window 3..15");
     static_assert(r <= kHalo, "halo must cover the window radius");
 };
@@ -123,35 +134,58 @@ __device__ __forceinline__ uint4 widen8(uint2 b) {
     return v;
 }
 
-// Stage rows y0-r .. y0+TH+r-1 and columns x0-kHalo .. x0+kTileW+kHalo-1 of the
-// frame in LDS (row-major, kLdsW values per row).  Coordinates outside the
-// frame are clamped to the nearest edge pixel.
+__device__ __forceinline__ uint4 splat8(uint32_t v) {
+    uint32_t p = v | (v << 16);
+    return make_uint4(p, p, p, p);
+}
+
+// One 8-pixel chunk of frame row gy starting at column gx, columns clamped to
+// the frame: a vector load when the chunk lies inside (and the layout is
+// 16-byte aligned), one pixel repeated when it lies wholly left or right of the
+// frame, per-pixel clamped loads when it straddles an edge.
+template <typename T>
+__device__ __forceinline__ uint4 load_chunk(const uint8_t *rp, int gx, int W, bool aligned) {
+    if (aligned && gx >= 0 && gx + 8 <= W) {
+        if constexpr (sizeof(T) == 2)
+            return *reinterpret_cast<const uint4 *>(rp + 2 * (uint64_t)gx);
+        else
+            return widen8(*reinterpret_cast<const uint2 *>(rp + gx));
+    }
+    if (gx + 8 <= 0) return splat8(load_px<T>(rp, 0));
+    if (gx >= W) return splat8(load_px<T>(rp, W - 1));
+    uint32_t e[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) e[i] = load_px<T>(rp, min(max(gx + i, 0), W - 1));
+    return make_uint4(e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16));
+}
+
+// Stage rows y0-r .. y0+TH+r-1 and columns x0-kHalo .. x0+kTileW+kHalo-1 of a
+// frame in LDS (row-major, kLdsPitch values apart), coordinates outside the
+// frame clamped to the nearest edge pixel.  All loads are issued before the
+// first LDS write.
 template <typename T, int K>
 __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
                                           int y0, bool aligned, uint16_t *tile) {
     using G = Geometry<K>;
-    for (int idx = threadIdx.x; idx < G::rows * kChunks; idx += kThreads) {
-        int row = idx / kChunks;
-        int c = idx - row * kChunks;
-        int gy = min(max(y0 - G::r + row, 0), H - 1);
-        int gx = x0 - kHalo + 8 * c;
-        const uint8_t *rp = src + (uint64_t)gy * pitch;
-        uint4 v;
-        if (aligned && gx >= 0 && gx + 8 <= W) {
-            if constexpr (sizeof(T) == 2)
-                v = *reinterpret_cast<const uint4 *>(rp + 2 * (uint64_t)gx);
-            else
-                v = widen8(*reinterpret_cast<const uint2 *>(rp + gx));
-        } else {
-            uint32_t e[8];
+    uint4 v[G::per_thread];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) e[i] = load_px<T>(rp, min(max(gx + i, 0), W - 1));
-            v.x = e[0] | (e[1] << 16);
-            v.y = e[2] | (e[3] << 16);
-            v.z = e[4] | (e[5] << 16);
-            v.w = e[6] | (e[7] << 16);
+    for (int i = 0; i < G::per_thread; ++i) {
+        const int idx = threadIdx.x + i * kThreads;
+        if (idx < G::chunks) {
+            const int row = idx / kChunks;
+            const int c = idx - row * kChunks;
+            const int gy = min(max(y0 - G::r + row, 0), H - 1);
+            v[i] = load_chunk<T>(src + (uint64_t)gy * pitch, x0 - kHalo + 8 * c, W, aligned);
         }
-        *reinterpret_cast<uint4 *>(tile + row * kLdsW + 8 * c) = v;
+    }
+#pragma unroll
+    for (int i = 0; i < G::per_thread; ++i) {
+        const int idx = threadIdx.x + i * kThreads;
+        if (idx < G::chunks) {
+            const int row = idx / kChunks;
+            const int c = idx - row * kChunks;
+            *reinterpret_cast<uint4 *>(tile + row * kLdsPitch + 8 * c) = v[i];
+        }
     }
 }
 
@@ -164,13 +198,19 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
 template <int r>
 __device__ __forceinline__ void row_minmax(const uint16_t *p, uint32_t &mn0, uint32_t &mn1,
                                            uint32_t &mx0, uint32_t &mx1, uint32_t &c0, uint32_t &c1) {
-    constexpr int JLO = -((r + 1) / 2);  // first pair needed
-    constexpr int JHI = (3 + r) / 2;     // last pair needed
+    // pairs JLO..JHI cover columns -r .. 3+r; the range is widened to whole
+    // 8-byte words so every LDS read is aligned
+    constexpr int JLO = (-((r + 1) / 2)) & ~1;
+    constexpr int JHI = ((3 + r) / 2) | 1;
     constexpr int NJ = JHI - JLO + 1;
-    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+    const uint2 *q = reinterpret_cast<const uint2 *>(p);
     uint32_t D[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) D[j] = q[j + JLO];
+    for (int j = 0; j < NJ; j += 2) {
+        const uint2 w = q[(j + JLO) / 2];
+        D[j] = w.x;
+        D[j + 1] = w.y;
+    }
     // V(o) = packed (pixel o, pixel o+1) relative to output column 0
     auto V = [&](int o) -> uint32_t {
         if ((o & 1) == 0) return D[o / 2 - JLO];
@@ -193,59 +233,71 @@ __device__ __forceinline__ void row_minmax(const uint16_t *p, uint32_t &mn0, uin
     c1 = D[1 - JLO];
 }
 
-// out[i] = op(h[i .. i+K-1]) for i < R by van Herk / Gil-Werman: block suffix
-// and prefix scans of length K, one combine per output.  Unused scan entries are
-// removed by the compiler.
-template <int K, int R, bool IS_MIN>
-__device__ __forceinline__ void sliding(const uint32_t (&h)[R + K - 1], uint32_t (&out)[R]) {
-    constexpr int L = R + K - 1;
-    auto op = [](uint32_t a, uint32_t b) { return IS_MIN ? pk_min(a, b) : pk_max(a, b); };
-    uint32_t suf[L], pre[L];
-#pragma unroll
-    for (int i = L - 1; i >= 0; --i)
-        suf[i] = (i % K == K - 1 || i == L - 1) ? h[i] : op(h[i], suf[i + 1]);
-#pragma unroll
-    for (int i = 0; i < L; ++i) pre[i] = (i % K == 0) ? h[i] : op(pre[i - 1], h[i]);
-#pragma unroll
-    for (int i = 0; i < R; ++i) out[i] = (i % K == 0) ? suf[i] : op(suf[i], pre[i + K - 1]);
-}
-
 // Flag bit layout inside a thread's 32-bit mask: bit q (+0, +16, +8, +24) is
 // column 0 (1, 2, 3) of output row q.
 __device__ __forceinline__ int bit_col(int b) { return (((b >> 3) & 1) << 1) | (b >> 4); }
 __device__ __forceinline__ int bit_row(int b) { return b & 7; }
 
 // Flags of the thread's 4 x R block (bit set = noisy).
+//
+// Rows are consumed in order.  The vertical window min/max of output row o is
+// op(suffix of the K-row block holding row o, from o; prefix of the next block,
+// up to o+K-1) -- van Herk / Gil-Werman with blocks of K rows.  A block's
+// suffixes are formed when its last row arrives, prefixes run as rows arrive,
+// and every output row is turned into flag bits as soon as both parts exist, so
+// only about one block of horizontal results is live at a time.
 template <int K>
-__device__ __forceinline__ uint32_t detect_block(const uint16_t *tile, int strip, int tx) {
+__device__ __forceinline__ uint32_t detect_block(const uint16_t *tile, int strip, int tx,
+                                                 uint32_t pk_one) {
     using G = Geometry<K>;
     constexpr int R = G::R, L = R + K - 1;
-    const uint16_t *base = tile + strip * R * kLdsW + kHalo + 4 * tx;
-    uint32_t hmn0[L], hmn1[L], hmx0[L], hmx1[L], c0[R], c1[R];
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
+    const uint16_t *base = tile + strip * R * kLdsPitch + kHalo + 4 * tx;
+    uint32_t mn0[L], mn1[L], mx0[L], mx1[L];  // horizontal results, then block suffixes
+    uint32_t pmn0[L], pmn1[L], pmx0[L], pmx1[L];  // running prefixes within a block
+    uint32_t c0[R], c1[R];
+    uint32_t flags = 0;
+    auto emit = [&](int o, uint32_t vmn0, uint32_t vmn1, uint32_t vmx0, uint32_t vmx1) {
+        // a half is zero exactly when the centre equals the window min or max;
+        // 1 - min(z, 1) turns that into one flag bit per half
+        const uint32_t z0 = pk_min(pk_subsat(c0[o], vmn0), pk_subsat(vmx0, c0[o]));
+        const uint32_t z1 = pk_min(pk_subsat(c1[o], vmn1), pk_subsat(vmx1, c1[o]));
+        const uint32_t f0 = pk_subsat(pk_one, z0);
+        const uint32_t f1 = pk_subsat(pk_one, z1);
+        flags |= (f0 | (f1 << 8)) << o;
+    };
+    static_for(std::make_integer_sequence<int, L>{}, [&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int blk = i / K, first = blk * K;
         uint32_t a, b;
-        row_minmax<G::r>(base + i * kLdsW, hmn0[i], hmn1[i], hmx0[i], hmx1[i], a, b);
-        if (i >= G::r && i < G::r + R) {
+        row_minmax<G::r>(base + i * kLdsPitch, mn0[i], mn1[i], mx0[i], mx1[i], a, b);
+        if constexpr (i >= G::r && i < G::r + R) {
             c0[i - G::r] = a;
             c1[i - G::r] = b;
         }
-    }
-    uint32_t vmn0[R], vmn1[R], vmx0[R], vmx1[R];
-    sliding<K, R, true>(hmn0, vmn0);
-    sliding<K, R, true>(hmn1, vmn1);
-    sliding<K, R, false>(hmx0, vmx0);
-    sliding<K, R, false>(hmx1, vmx1);
-    uint32_t keep = 0;  // bit set = signal pixel
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        // a half is zero exactly when the centre equals the window min or max
-        uint32_t z0 = pk_min(pk_subsat(c0[q], vmn0[q]), pk_subsat(vmx0[q], c0[q]));
-        uint32_t z1 = pk_min(pk_subsat(c1[q], vmn1[q]), pk_subsat(vmx1[q], c1[q]));
-        keep |= pk_min(z0, 0x00010001u) << q;
-        keep |= pk_min(z1, 0x00010001u) << (q + 8);
-    }
-    return ~keep;
+        // running prefix of this block
+        if constexpr (i == first) {
+            pmn0[i] = mn0[i]; pmn1[i] = mn1[i]; pmx0[i] = mx0[i]; pmx1[i] = mx1[i];
+        } else {
+            pmn0[i] = pk_min(pmn0[i - 1], mn0[i]); pmn1[i] = pk_min(pmn1[i - 1], mn1[i]);
+            pmx0[i] = pk_max(pmx0[i - 1], mx0[i]); pmx1[i] = pk_max(pmx1[i - 1], mx1[i]);
+        }
+        // output o = i-K+1 straddling two blocks: suffix of its block + this prefix
+        constexpr int o = i - K + 1;
+        if constexpr (o >= 0 && o < R && o % K != 0)
+            emit(o, pk_min(mn0[o], pmn0[i]), pk_min(mn1[o], pmn1[i]), pk_max(mx0[o], pmx0[i]),
+                 pk_max(mx1[o], pmx1[i]));
+        // block complete: suffixes in place, and the output that starts the block
+        if constexpr (i % K == K - 1 || i == L - 1) {
+            static_for(std::make_integer_sequence<int, i - first>{}, [&](auto jc) {
+                constexpr int j = i - 1 - decltype(jc)::value;
+                mn0[j] = pk_min(mn0[j], mn0[j + 1]); mn1[j] = pk_min(mn1[j], mn1[j + 1]);
+                mx0[j] = pk_max(mx0[j], mx0[j + 1]); mx1[j] = pk_max(mx1[j], mx1[j + 1]);
+            });
+            if constexpr (first < R && i - first == K - 1)
+                emit(first, mn0[first], mn1[first], mx0[first], mx1[first]);
+        }
+    });
+    return flags;
 }
 
 // Bits of the thread's block that lie inside the frame.
@@ -266,8 +318,11 @@ __device__ __forceinline__ uint32_t valid_bits(int R, int W, int H, int px, int 
 // Window element i (row-major) of the window whose top-left LDS value is w.
 template <int K>
 __device__ __forceinline__ uint32_t win_pair(const uint16_t *w0, const uint16_t *w1, int i) {
-    int off = (i / K) * kLdsW + (i % K);
-    return (uint32_t)w0[off] | ((uint32_t)w1[off] << 16);
+    const int off = (i / K) * kLdsPitch + (i % K);
+    u16x2 v;  // element-wise build lets the compiler load straight into each half
+    v.x = w0[off];
+    v.y = w1[off];
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 template <int... I, typename F>
@@ -275,36 +330,93 @@ __device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &
     (f(std::integral_constant<int, I>{}), ...);
 }
 
-// Forgetful selection: sort the first M = (n+3)/2 values (odd-even merge
-// network), drop the two ends (neither can be the median of n), then for each
-// remaining value insert it into the sorted run and drop both ends again.  After
-// the last value the run holds one element: the median.  Insertion of x into a
-// sorted run s, ends dropped, is s'[i] = max(s[i], min(s[i+1], x)).
-template <int K>
-__device__ __forceinline__ uint32_t median_forgetful(const uint16_t *w0, const uint16_t *w1) {
-    constexpr int N = K * K;
-    constexpr int M = (N + 3) / 2;
-    uint32_t a[M];
-#pragma unroll
-    for (int i = 0; i < M; ++i) a[i] = win_pair<K>(w0, w1, i);
-    static_for(std::make_integer_sequence<int, net::Network<M>::size>{}, [&](auto c) {
-        constexpr int i = net::network<M>.lo[decltype(c)::value];
-        constexpr int j = net::network<M>.hi[decltype(c)::value];
-        uint32_t lo = pk_min(a[i], a[j]);
-        uint32_t hi = pk_max(a[i], a[j]);
-        a[i] = lo;
-        a[j] = hi;
+// Compare-exchange of two packed pairs (both halves at once).
+__device__ __forceinline__ void cex(uint32_t &a, uint32_t &b) {
+    const uint32_t lo = pk_min(a, b);
+    b = pk_max(a, b);
+    a = lo;
+}
+
+// Sort a[0..N) with the odd-even merge network (indices are compile-time).
+template <int N>
+__device__ __forceinline__ void sort_block(uint32_t *a) {
+    static_for(std::make_integer_sequence<int, net::Network<N>::size>{}, [&](auto c) {
+        constexpr int i = net::network<N>.lo[decltype(c)::value];
+        constexpr int j = net::network<N>.hi[decltype(c)::value];
+        cex(a[i], a[j]);
     });
-    // run = a[1 .. M-2]
+}
+
+// Merge sorted a[0..L) and sorted b[0..S) into out[0..L+S).  Both halves of the
+// merge network are padded with 0xffff (+infinity for 16-bit values); the
+// compiler folds every comparison against the padding constant.
+template <int L, int S>
+__device__ __forceinline__ void merge_sorted(const uint32_t *a, const uint32_t *b, uint32_t *out) {
+    constexpr int P = net::pow2_at_least(L > S ? L : S);
+    uint32_t x[2 * P];
 #pragma unroll
-    for (int t = 0; t < N - M; ++t) {
-        uint32_t x = win_pair<K>(w0, w1, M + t);
-        int L = M - 2 - t;  // current run length, run at a[1 .. L]
-#pragma unroll
-        for (int i = 1; i < M - 1; ++i)
-            if (i < L) a[i] = pk_max(a[i], pk_min(a[i + 1], x));
+    for (int i = 0; i < P; ++i) {
+        x[i] = i < L ? a[i] : 0xffffffffu;
+        x[P + i] = i < S ? b[i] : 0xffffffffu;
     }
-    return a[1];
+    static_for(std::make_integer_sequence<int, net::MergeNetwork<P>::size>{}, [&](auto c) {
+        constexpr int i = net::merge_network<P>.lo[decltype(c)::value];
+        constexpr int j = net::merge_network<P>.hi[decltype(c)::value];
+        cex(x[i], x[j]);
+    });
+#pragma unroll
+    for (int i = 0; i < L + S; ++i) out[i] = x[i];
+}
+
+// Block sizes of the forgetful selection (first block, later blocks).
+template <int K>
+struct BlockPlan {
+    static constexpr int N = K * K;
+    static constexpr int block = K <= 3 ? 4 : (K <= 5 ? 8 : 16);
+    static constexpr int size_at(int pos) { return block < N - pos ? block : N - pos; }
+    static constexpr int max_run = 64;
+};
+
+// Forgetful selection over sorted blocks.  State: a sorted run of L values, the
+// rank T (0-based) that the median has among the run plus the N-POS values not
+// yet read.  Each step sorts the next block, merges it into the run and drops
+// every value that cannot have rank T: the DLOW smallest (even if all unread
+// values were smaller they would still rank below T) and the DHIGH largest
+// (more than T run values lie below them).  When every value has been read the
+// run holds exactly one value, the median.
+template <int K, int POS, int L, int T>
+__device__ __forceinline__ uint32_t select_blocks(const uint32_t *run, const uint16_t *w0,
+                                                  const uint16_t *w1) {
+    constexpr int N = K * K;
+    if constexpr (POS == N) {
+        static_assert(L == 1, "forgetful selection must end with one value");
+        return run[0];
+    } else {
+        constexpr int S = BlockPlan<K>::size_at(POS);
+        constexpr int M = L + S;
+        constexpr int U = N - POS - S;
+        constexpr int DLOW = T - U > 0 ? T - U : 0;
+        constexpr int DHIGH = M - 1 - T > 0 ? M - 1 - T : 0;
+        constexpr int NL = M - DLOW - DHIGH;
+        static_assert(M <= 2 * BlockPlan<K>::max_run, "run too long");
+        uint32_t blk[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) blk[i] = win_pair<K>(w0, w1, POS + i);
+        sort_block<S>(blk);
+        uint32_t merged[M];
+        if constexpr (L == 0) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) merged[i] = blk[i];
+        } else {
+            merge_sorted<L, S>(run, blk, merged);
+        }
+        return select_blocks<K, POS + S, NL, T - DLOW>(merged + DLOW, w0, w1);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t median_blocks(const uint16_t *w0, const uint16_t *w1) {
+    return select_blocks<K, 0, 0, (K * K - 1) / 2>(nullptr, w0, w1);
 }
 
 // Bisection on grey level: the median is the smallest value t with more than
@@ -344,8 +456,8 @@ __device__ __forceinline__ uint32_t median_bisect(const uint16_t *w0, const uint
 
 template <int K>
 __device__ __forceinline__ uint32_t median_pair(const uint16_t *w0, const uint16_t *w1) {
-    if constexpr (K <= 7)
-        return median_forgetful<K>(w0, w1);
+    if constexpr (K <= 9)
+        return median_blocks<K>(w0, w1);
     else
         return median_bisect<K>(w0, w1);
 }
@@ -397,25 +509,40 @@ __device__ __forceinline__ void store4(uint8_t *row, int px, int W, bool aligned
 // ---------------------------------------------------------------------------
 // the tile kernel
 // ---------------------------------------------------------------------------
-// Workgroups are handed to the 8 XCDs round-robin; renumber them so each XCD
-// walks a contiguous range of tiles (neighbouring tiles share halo rows in the
-// XCD's L2).
-__device__ __forceinline__ int xcd_tile(int b, int n) {
+// Tiles of a launch are split into 8 contiguous ranges, one per XCD (the
+// hardware hands workgroup b to XCD b % 8); the workgroups of an XCD stride
+// through its range, so tiles that share halo rows run close together in time
+// and on the same L2.  Each range's length is proportional to its workgroups.
+struct TileRange {
+    int first, end, stride;
+};
+
+__device__ __forceinline__ TileRange xcd_range(int b, int G, int total) {
     constexpr int X = 8;
-    int per = (n + X - 1) / X;
-    int tall = n % X == 0 ? X : n % X;
-    int xcd = b % X, local = b / X;
-    return xcd < tall ? xcd * per + local : tall * per + (xcd - tall) * (per - 1) + local;
+    const int xcd = b % X, local = b / X;
+    const int per = G / X, extra = G % X;
+    const int nx = per + (xcd < extra ? 1 : 0);           // workgroups on this XCD
+    const int before = xcd * per + (xcd < extra ? xcd : extra);  // workgroups on lower XCDs
+    const int tb = (int)((long long)total * before / G);
+    const int te = (int)((long long)total * (before + nx) / G);
+    return {tb + local, te, nx};
 }
 
+template <int K>
+struct TileSmem {
+    using G = Geometry<K>;
+    uint16_t tile[G::rows * kLdsPitch];
+    uint16_t list[G::tile_px];  // LDS offsets of flagged centres, then their medians
+    uint32_t count;             // list length
+};
+
+// One tile already staged in LDS: detection, compaction of the flagged pixels,
+// selection, then the tile (flagged pixels replaced) is stored.  Returns the
+// number of flagged pixels the calling wave found (wave-uniform).
 template <typename T, int K, int MODE>
-__device__ __forceinline__ void filter_tile(const StackArgs &a, int tile) {
+__device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K> &sm) {
     using G = Geometry<K>;
     constexpr int R = G::R;
-    __shared__ __attribute__((aligned(16))) uint16_t lds_tile[G::rows * kLdsW];
-    __shared__ uint16_t lds_list[G::tile_px];
-    __shared__ uint32_t lds_wave[kThreads / 64];
-
     const int f = tile / a.tiles_per_frame;
     const int rem = tile - f * a.tiles_per_frame;
     const int ty = rem / a.tiles_x;
@@ -428,13 +555,9 @@ __device__ __forceinline__ void filter_tile(const StackArgs &a, int tile) {
     const int px = x0 + 4 * tx, py = y0 + strip * R;
     const uint32_t valid = valid_bits(R, W, H, px, py);
 
-    const uint8_t *src = a.src + (uint64_t)f * a.src_stride;
-    load_tile<T, K>(src, a.src_pitch, W, H, x0, y0, aligned, lds_tile);
-    __syncthreads();
-
     uint32_t flags;
     if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR) {
-        flags = detect_block<K>(lds_tile, strip, tx) & valid;
+        flags = detect_block<K>(sm.tile, strip, tx, a.pk_one) & valid;
     } else if constexpr (MODE == MODE_MEDIAN_MASK) {
         flags = 0;
         const uint8_t *m = a.mask_in + (uint64_t)f * a.mask_stride;
@@ -445,7 +568,7 @@ __device__ __forceinline__ void filter_tile(const StackArgs &a, int tile) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if (px + e < W && mr[px + e] != 0) {
-                    int sh = (e == 0) ? 0 : (e == 1) ? 16 : (e == 2) ? 8 : 24;
+                    const int sh = (e == 0) ? 0 : (e == 1) ? 16 : (e == 2) ? 8 : 24;
                     flags |= 1u << (q + sh);
                 }
             }
@@ -454,68 +577,65 @@ __device__ __forceinline__ void filter_tile(const StackArgs &a, int tile) {
         flags = valid;
     }
 
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
     const uint32_t cnt = __builtin_popcount(flags);
     const uint32_t incl = wave_inclusive_sum(cnt);
-    if (lane == 63) lds_wave[wave] = incl;
-    __syncthreads();
-    uint32_t base = incl - cnt, total = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
-        uint32_t t = lds_wave[w];
-        if (w < wave) base += t;
-        total += t;
-    }
-
-    if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR) {
-        if (a.count != nullptr && tid == 0 && total != 0) atomicAdd(a.count, (unsigned long long)total);
-    }
+    const uint32_t wave_total = __builtin_amdgcn_readlane(incl, 63);
 
     if constexpr (MODE == MODE_DETECT) {
         uint8_t *m = a.mask_out + (uint64_t)f * a.mask_stride;
+#pragma unroll
         for (int q = 0; q < R; ++q) {
             if (py + q >= H) break;
             uint8_t *mr = m + (uint64_t)(py + q) * a.mask_pitch;
-            uint32_t b0 = (flags >> q) & 1u, b1 = (flags >> (q + 16)) & 1u;
-            uint32_t b2 = (flags >> (q + 8)) & 1u, b3 = (flags >> (q + 24)) & 1u;
+            const uint32_t b0 = (flags >> q) & 1u, b1 = (flags >> (q + 16)) & 1u;
+            const uint32_t b2 = (flags >> (q + 8)) & 1u, b3 = (flags >> (q + 24)) & 1u;
             if (aligned && px + 4 <= W) {
                 *reinterpret_cast<uint32_t *>(mr + px) = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
             } else {
-                uint32_t e[4] = {b0, b1, b2, b3};
+                const uint32_t e[4] = {b0, b1, b2, b3};
                 for (int i = 0; i < 4; ++i)
                     if (px + i < W) mr[px + i] = (uint8_t)e[i];
             }
         }
-        return;
+        return wave_total;
     } else {
-        // 3. compaction: LDS offsets of the flagged pixels' centres
-        const int centre0 = (strip * R + G::r) * kLdsW + kHalo + 4 * tx;
+        // 3. compaction: one LDS atomic per wave reserves the wave's list slots;
+        //    a thread's entries are contiguous and in flag-bit order
+        uint32_t wbase = 0;
+        if (lane == 63 && wave_total != 0) wbase = atomicAdd(&sm.count, wave_total);
+        const uint32_t first = __builtin_amdgcn_readlane(wbase, 63) + incl - cnt;
+        const int centre0 = (strip * R + G::r) * kLdsPitch + kHalo + 4 * tx;
         {
-            uint32_t m = flags, j = base;
+            uint32_t m = flags, j = first;
             while (m) {
-                int b = __builtin_ctz(m);
+                const int b = __builtin_ctz(m);
                 m &= m - 1;
-                lds_list[j++] = (uint16_t)(centre0 + bit_row(b) * kLdsW + bit_col(b));
+                sm.list[j++] = (uint16_t)(centre0 + bit_row(b) * kLdsPitch + bit_col(b));
             }
         }
         __syncthreads();
-        // 4. medians, two list entries per lane
-        const int corner = G::r * kLdsW + G::r;
-        for (uint32_t i = 2 * tid; i < total; i += 2 * kThreads) {
-            uint32_t e0 = lds_list[i];
-            uint32_t e1 = (i + 1 < total) ? lds_list[i + 1] : e0;
-            uint32_t med = median_pair<K>(lds_tile + e0 - corner, lds_tile + e1 - corner);
-            lds_list[i] = (uint16_t)(med & 0xffffu);
-            if (i + 1 < total) lds_list[i + 1] = (uint16_t)(med >> 16);
+        const uint32_t total = sm.count;
+        // 4. medians, two list entries per lane, consecutive lanes first so
+        //    that as few waves as possible run the selection; which wave starts
+        //    the list rotates with the tile (waves sit on fixed SIMDs)
+        constexpr int corner = G::r * kLdsPitch + G::r;
+        const uint32_t slot = (uint32_t)(tid + 64 * (tile & 3)) % kThreads;
+        for (uint32_t i = 2 * slot; i < total; i += 2 * kThreads) {
+            const uint32_t e0 = sm.list[i];
+            const uint32_t e1 = (i + 1 < total) ? sm.list[i + 1] : e0;
+            const uint32_t med = median_pair<K>(sm.tile + e0 - corner, sm.tile + e1 - corner);
+            sm.list[i] = (uint16_t)(med & 0xffffu);
+            if (i + 1 < total) sm.list[i + 1] = (uint16_t)(med >> 16);
         }
         __syncthreads();
         // results back into the tile at the thread's own pixels
         {
-            uint32_t m = flags, j = base;
+            uint32_t m = flags, j = first;
             while (m) {
-                int b = __builtin_ctz(m);
+                const int b = __builtin_ctz(m);
                 m &= m - 1;
-                lds_tile[centre0 + bit_row(b) * kLdsW + bit_col(b)] = lds_list[j++];
+                sm.tile[centre0 + bit_row(b) * kLdsPitch + bit_col(b)] = sm.list[j++];
             }
         }
         // 5. store the thread's block (its own LDS values only: no barrier needed)
@@ -523,15 +643,47 @@ __device__ __forceinline__ void filter_tile(const StackArgs &a, int tile) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if (py + q >= H) break;
-            const uint32_t *c = reinterpret_cast<const uint32_t *>(lds_tile + centre0 + q * kLdsW);
+            const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * kLdsPitch);
             store4<T>(dst + (uint64_t)(py + q) * a.dst_pitch, px, W, aligned, c[0], c[1]);
         }
+        return wave_total;
     }
 }
 
+__device__ __forceinline__ void tile_origin(const StackArgs &a, int tile, int th, int &f, int &x0,
+                                            int &y0) {
+    f = tile / a.tiles_per_frame;
+    const int rem = tile - f * a.tiles_per_frame;
+    const int ty = rem / a.tiles_x;
+    x0 = (rem - ty * a.tiles_x) * kTileW;
+    y0 = ty * th;
+}
+
+// Persistent kernel: every workgroup loops over its tile range.  Four
+// barriers per tile: before the LDS tile is overwritten, after it is written,
+// after the flagged list is complete and after the selection.  Other resident
+// workgroups run while one waits for its tile's loads.
 template <typename T, int K, int MODE>
-__global__ __launch_bounds__(kThreads) void fnr_stack_kernel(StackArgs a) {
-    filter_tile<T, K, MODE>(a, xcd_tile(blockIdx.x, a.total_tiles));
+__global__ __launch_bounds__(kThreads) void fnr_persistent_kernel(StackArgs a) {
+    using G = Geometry<K>;
+    __shared__ __attribute__((aligned(16))) TileSmem<K> sm;
+    const TileRange rg = xcd_range(blockIdx.x, gridDim.x, a.total_tiles);
+    const bool aligned = a.aligned != 0;
+    uint32_t flagged = 0;  // this wave's noisy pixels over all its tiles
+    for (int t = rg.first; t < rg.end; t += rg.stride) {
+        int f, x0, y0;
+        tile_origin(a, t, G::TH, f, x0, y0);
+        __syncthreads();  // the previous tile is no longer read
+        load_tile<T, K>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, a.width, a.height, x0, y0,
+                        aligned, sm.tile);
+        if (threadIdx.x == 0) sm.count = 0;
+        __syncthreads();
+        flagged += process_tile<T, K, MODE>(a, t, sm);
+    }
+    if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR) {
+        if (a.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)
+            atomicAdd(a.count, (unsigned long long)flagged);
+    }
 }
 
 __global__ void zero_u64_kernel(unsigned long long *p, int n) {

@@ -55,9 +55,37 @@ int tile_rows(int window) {
     return kStrips * Geometry<3>::R;  // every window uses the same tile height
 }
 
+int device_cus() {
+    static const int cus = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+            n = 256;
+        return n;
+    }();
+    return cus;
+}
+
+// Persistent grid: as many workgroups as fit on the device at once (never more
+// than there are tiles).
+template <typename T, int K, int MODE>
+int persistent_grid(int total_tiles) {
+    static const int per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_persistent_kernel<T, K, MODE>, kThreads,
+                                                         0) != hipSuccess ||
+            n < 1)
+            n = 1;
+        return n;
+    }();
+    const long long g = (long long)per_cu * device_cus();
+    return (int)(g < total_tiles ? g : total_tiles);
+}
+
 template <typename T, int K, int MODE>
 void launch_t(const StackArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((fnr_stack_kernel<T, K, MODE>), dim3(a.total_tiles), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((fnr_persistent_kernel<T, K, MODE>), dim3(persistent_grid<T, K, MODE>(a.total_tiles)),
+                       dim3(kThreads), 0, s, a);
 }
 
 template <typename T, int MODE>
@@ -84,6 +112,7 @@ irf_status launch(irf_dtype dtype, int window, int nframes, StackArgs a, hipStre
     if (total > 0x7fffffffull) return IRF_ERR_DIMS;
     a.tiles_per_frame = (int)per_frame;
     a.total_tiles = (int)total;
+    a.pk_one = 0x00010001u;
     (void)hipGetLastError();
     bool ok = dtype == IRF_U8 ? launch_k<uint8_t, MODE>(window, a, s)
                               : launch_k<uint16_t, MODE>(window, a, s);

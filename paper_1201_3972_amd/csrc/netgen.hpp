@@ -49,5 +49,46 @@ struct Network {
 template <int N>
 inline constexpr Network<N> network{};
 
+// The last stage of the odd-even merge sort on 2P inputs: it merges two sorted
+// halves [0, P) and [P, 2P) into one sorted sequence (Batcher's merge).
+template <typename F>
+constexpr void odd_even_merge_stage(int P, F &&f) {
+    const int n = 2 * P, p = P;
+    for (int k = p; k >= 1; k /= 2)
+        for (int j = k % p; j + k <= n - 1; j += 2 * k)
+            for (int i = 0; i <= imin(k - 1, n - j - k - 1); ++i)
+                if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) f(i + j, i + j + k);
+}
+
+constexpr int count_merge_comparators(int P) {
+    int c = 0;
+    odd_even_merge_stage(P, [&](int, int) { ++c; });
+    return c;
+}
+
+template <int P>
+struct MergeNetwork {
+    static constexpr int size = count_merge_comparators(P);
+    int lo[size > 0 ? size : 1];
+    int hi[size > 0 ? size : 1];
+    constexpr MergeNetwork() : lo(), hi() {
+        int c = 0;
+        odd_even_merge_stage(P, [&](int i, int j) {
+            lo[c] = i;
+            hi[c] = j;
+            ++c;
+        });
+    }
+};
+
+template <int P>
+inline constexpr MergeNetwork<P> merge_network{};
+
+constexpr int pow2_at_least(int n) {
+    int p = 1;
+    while (p < n) p *= 2;
+    return p;
+}
+
 }  // namespace net
 }  // namespace irf

@@ -120,6 +120,57 @@ irf_status ir_filter_run_frames(const void *src, size_t src_pitch, size_t src_st
                                 size_t scratch_pitch, size_t scratch_stride,
                                 uint64_t *flagged_count, hipStream_t stream);
 
+/*
+ * Batches of uneven frames (one persistent launch over all their tiles).
+ *
+ * irf_frame describes one frame: device src/dst, pitches, size, pixel type and
+ * window; frames of a batch are independent and may all differ.  Every frame
+ * is filtered once with the FNR filter (same result as ir_filter_run with
+ * passes = 1).  Frames with windows 3..9 share one persistent kernel; frames
+ * with windows 11..15 share a second one, launched after it on the same stream.
+ */
+typedef struct {
+    const void *src;
+    void *dst;
+    size_t src_pitch, dst_pitch;
+    int width, height;
+    irf_dtype dtype;
+    int window;
+} irf_frame;
+
+typedef struct irf_plan irf_plan;
+
+#define IRF_PLAN_GRAPH 1u /* replay the batch kernels from a captured hipGraph */
+
+/*
+ * ir_filter_plan_create -- allocate a plan for batches of at most max_frames
+ * frames holding at most max_tiles tiles in total (a frame of W x H has
+ * ceil(W/128) * ceil(H/64) tiles).  The plan owns two sets of device tables
+ * (frame descriptors, tile map, work queues) with pinned host staging, used
+ * alternately by consecutive batches; it is not thread-safe.  Returns
+ * IRF_ERR_NOMEM or IRF_ERR_HIP on failure (*plan is then NULL).
+ */
+irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles, unsigned flags);
+
+/*
+ * ir_filter_run_batch -- filter n frames (1 <= n <= max_frames) on `stream`.
+ *   frames          host array of n descriptors (read before the call returns)
+ *   flagged_counts  nullable device array of n uint64: noisy pixels per frame
+ *                   (zeroed on the stream, then accumulated)
+ * Validation covers every frame as in ir_filter_run, and no frame's dst may
+ * overlap any frame's src or dst (IRF_ERR_ALIAS); a batch over the plan's
+ * capacity returns IRF_ERR_CAPACITY.  May block the host until the batch
+ * submitted two calls earlier on this plan has finished copying its tables.
+ */
+irf_status ir_filter_run_batch(irf_plan *plan, const irf_frame *frames, int n,
+                               uint64_t *flagged_counts, hipStream_t stream);
+
+/* Release a plan (waits for its outstanding work).  NULL is ignored. */
+void ir_filter_plan_destroy(irf_plan *plan);
+
+/* Tiles of one frame as counted against a plan's max_tiles. */
+int ir_filter_frame_tiles(int width, int height);
+
 /* Human-readable name of a status code (static string, never NULL). */
 const char *ir_filter_status_string(irf_status status);
 

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_PATH = os.path.join(PKG, "libirfilter.so")
-SOURCES = [os.path.join(CSRC, "irfilter.hip")]
+SOURCES = [os.path.join(CSRC, "irfilter.hip"), os.path.join(CSRC, "batch.hip")]
 ARCH = os.environ.get("IRF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

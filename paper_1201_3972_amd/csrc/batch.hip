@@ -1,0 +1,297 @@
+// batch.hip -- plans and batched launches over frames of uneven size, pixel
+// type and window (see include/irfilter.h and batch_device.hpp).
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/irfilter.h"
+#include "batch_device.hpp"
+#include "host_common.hpp"
+
+using namespace irf;
+using namespace irf::host;
+
+namespace {
+
+constexpr int kSets = 2;          // device table sets used alternately
+constexpr size_t kQueueBytes = 64;  // two BatchQueue records
+
+int frame_tiles(int width, int height) {
+    const int th = kStrips * Geometry<3>::R;
+    return ((width + kTileW - 1) / kTileW) * ((height + th - 1) / th);
+}
+
+template <int CLASS>
+int batch_grid() {
+    static const int per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_batch_kernel<CLASS>, kThreads, 0) !=
+                hipSuccess ||
+            n < 1)
+            n = 1;
+        return n;
+    }();
+    return per_cu * device_cus();
+}
+
+}  // namespace
+
+// Device layout of one table set: [queues (64 B) | descriptors | tile map].
+struct irf_plan {
+    int max_frames = 0, max_tiles = 0;
+    unsigned flags = 0;
+    size_t desc_off = 0, map_off = 0, bytes = 0;
+    int grid[2] = {0, 0};
+    int next_set = 0;
+    struct Set {
+        unsigned char *dev = nullptr;
+        unsigned char *host = nullptr;  // pinned staging
+        hipEvent_t copied = nullptr;    // staging may be rewritten
+        hipEvent_t done = nullptr;      // device tables may be rewritten
+        hipGraphExec_t graph = nullptr;
+        bool used = false;
+    } set[kSets];
+};
+
+namespace {
+
+// Each window class has its own queue and its own region of the tile map
+// (class c at map + c * max_tiles), so the arguments of both kernels are fixed
+// per table set and can be captured in a graph once.  `classes` selects the
+// kernels (bit c = class c).
+void launch_batch(const irf_plan *p, const irf_plan::Set &s, unsigned classes, hipStream_t stream) {
+    BatchQueue *q = reinterpret_cast<BatchQueue *>(s.dev);
+    const FrameDesc *d = reinterpret_cast<const FrameDesc *>(s.dev + p->desc_off);
+    const uint32_t *map = reinterpret_cast<const uint32_t *>(s.dev + p->map_off);
+    if (classes & 1u)
+        hipLaunchKernelGGL(fnr_batch_kernel<0>, dim3(p->grid[0]), dim3(kThreads), 0, stream, d, map, q,
+                           0x00010001u);
+    if (classes & 2u)
+        hipLaunchKernelGGL(fnr_batch_kernel<1>, dim3(p->grid[1]), dim3(kThreads), 0, stream, d,
+                           map + p->max_tiles, q + 1, 0x00010001u);
+}
+
+void free_plan(irf_plan *p) {
+    if (!p) return;
+    for (auto &s : p->set) {
+        if (s.graph) (void)hipGraphExecDestroy(s.graph);
+        if (s.copied) (void)hipEventDestroy(s.copied);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.host) (void)hipHostFree(s.host);
+    }
+    delete p;
+}
+
+// Every dst span must be disjoint from every other span (src or dst).
+bool batch_aliases(const irf_frame *frames, int n) {
+    struct Ev {
+        uintptr_t lo, hi;
+        bool dst;
+    };
+    std::vector<Ev> ev;
+    ev.reserve(2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const int b = bytes_of(frames[i].dtype);
+        const Span s = span_of(frames[i].src, frames[i].src_pitch, 0, frames[i].width, frames[i].height, 1, b);
+        const Span d = span_of(frames[i].dst, frames[i].dst_pitch, 0, frames[i].width, frames[i].height, 1, b);
+        ev.push_back({s.lo, s.hi, false});
+        ev.push_back({d.lo, d.hi, true});
+    }
+    std::sort(ev.begin(), ev.end(), [](const Ev &a, const Ev &b) { return a.lo < b.lo; });
+    uintptr_t end_any = 0, end_dst = 0;
+    for (const Ev &e : ev) {
+        if (e.dst ? e.lo < end_any : e.lo < end_dst) return true;
+        end_any = std::max(end_any, e.hi);
+        if (e.dst) end_dst = std::max(end_dst, e.hi);
+    }
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ir_filter_frame_tiles(int width, int height) {
+    if (width < 1 || height < 1 || width > IRF_MAX_DIM || height > IRF_MAX_DIM) return 0;
+    return frame_tiles(width, height);
+}
+
+irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles, unsigned flags) {
+    if (!plan) return IRF_ERR_NULL;
+    *plan = nullptr;
+    if (max_frames < 1 || max_tiles < 1 || max_frames > (1 << 24) || max_tiles > (1 << 28))
+        return IRF_ERR_DIMS;
+    irf_plan *p = new (std::nothrow) irf_plan();
+    if (!p) return IRF_ERR_NOMEM;
+    try {
+        p->max_frames = max_frames;
+        p->max_tiles = max_tiles;
+        p->flags = flags;
+        p->desc_off = kQueueBytes;
+        p->map_off = p->desc_off + sizeof(FrameDesc) * (size_t)max_frames;
+        p->bytes = p->map_off + sizeof(uint32_t) * 2 * (size_t)max_tiles;
+        (void)hipGetLastError();
+        p->grid[0] = batch_grid<0>();
+        p->grid[1] = batch_grid<1>();
+        for (auto &s : p->set) {
+            if (hipMalloc(&s.dev, p->bytes) != hipSuccess) {
+                free_plan(p);
+                (void)hipGetLastError();
+                return IRF_ERR_NOMEM;
+            }
+            if (hipHostMalloc(&s.host, p->bytes, hipHostMallocDefault) != hipSuccess) {
+                free_plan(p);
+                (void)hipGetLastError();
+                return IRF_ERR_NOMEM;
+            }
+            if (hipEventCreateWithFlags(&s.copied, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+                free_plan(p);
+                (void)hipGetLastError();
+                return IRF_ERR_HIP;
+            }
+        }
+        if (flags & IRF_PLAN_GRAPH) {
+            hipStream_t cs = nullptr;
+            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+                free_plan(p);
+                (void)hipGetLastError();
+                return IRF_ERR_HIP;
+            }
+            bool ok = true;
+            for (auto &s : p->set) {
+                hipGraph_t g = nullptr;
+                ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) launch_batch(p, s, 3u, cs);
+                ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok;
+                ok = ok && hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0) == hipSuccess;
+                if (g) (void)hipGraphDestroy(g);
+                if (!ok) break;
+            }
+            (void)hipStreamDestroy(cs);
+            if (!ok) {
+                free_plan(p);
+                (void)hipGetLastError();
+                return IRF_ERR_HIP;
+            }
+        }
+        *plan = p;
+        return IRF_OK;
+    } catch (...) {
+        free_plan(p);
+        return IRF_ERR_NOMEM;
+    }
+}
+
+irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint64_t *counts,
+                               hipStream_t stream) {
+    try {
+        if (!p || !frames) return IRF_ERR_NULL;
+        if (n < 1) return IRF_ERR_DIMS;
+        if (n > p->max_frames) return IRF_ERR_CAPACITY;
+        long long tiles[2] = {0, 0};
+        for (int i = 0; i < n; ++i) {
+            const irf_frame &f = frames[i];
+            if (!f.src || !f.dst) return IRF_ERR_NULL;
+            irf_status st = check_common(f.width, f.height, 1, f.dtype, f.window);
+            if (st) return st;
+            const int b = bytes_of(f.dtype);
+            if ((st = check_layout(f.src_pitch, 0, f.width, f.height, 1, b))) return st;
+            if ((st = check_layout(f.dst_pitch, 0, f.width, f.height, 1, b))) return st;
+            tiles[batch_class(f.window)] += frame_tiles(f.width, f.height);
+        }
+        if (tiles[0] > p->max_tiles || tiles[1] > p->max_tiles) return IRF_ERR_CAPACITY;
+        if (batch_aliases(frames, n)) return IRF_ERR_ALIAS;
+        if (counts) {
+            const Span cs = {reinterpret_cast<uintptr_t>(counts),
+                             reinterpret_cast<uintptr_t>(counts) + sizeof(uint64_t) * (size_t)n};
+            for (int i = 0; i < n; ++i) {
+                const int b = bytes_of(frames[i].dtype);
+                if (overlap(cs, span_of(frames[i].dst, frames[i].dst_pitch, 0, frames[i].width,
+                                        frames[i].height, 1, b)) ||
+                    overlap(cs, span_of(frames[i].src, frames[i].src_pitch, 0, frames[i].width,
+                                        frames[i].height, 1, b)))
+                    return IRF_ERR_ALIAS;
+            }
+        }
+
+        (void)hipGetLastError();
+        irf_plan::Set &s = p->set[p->next_set];
+        p->next_set = (p->next_set + 1) % kSets;
+        if (s.used && hipEventSynchronize(s.copied) != hipSuccess) return IRF_ERR_HIP;
+
+        // host staging: queues, descriptors, tile map (class 0 region, then class 1)
+        BatchQueue *q = reinterpret_cast<BatchQueue *>(s.host);
+        FrameDesc *d = reinterpret_cast<FrameDesc *>(s.host + p->desc_off);
+        uint32_t *map = reinterpret_cast<uint32_t *>(s.host + p->map_off);
+        memset(q, 0, kQueueBytes);
+        q[0].total = (unsigned)tiles[0];
+        q[1].total = (unsigned)tiles[1];
+        int begin[2] = {0, 0};
+        for (int i = 0; i < n; ++i) {
+            const irf_frame &f = frames[i];
+            const int b = bytes_of(f.dtype), c = batch_class(f.window), nt = frame_tiles(f.width, f.height);
+            FrameDesc &e = d[i];
+            e.src = static_cast<const uint8_t *>(f.src);
+            e.dst = static_cast<uint8_t *>(f.dst);
+            e.src_pitch = f.src_pitch;
+            e.dst_pitch = f.dst_pitch;
+            e.count = counts ? reinterpret_cast<unsigned long long *>(counts + i) : nullptr;
+            e.width = f.width;
+            e.height = f.height;
+            e.tiles_x = (f.width + kTileW - 1) / kTileW;
+            e.tiles = nt;
+            e.tile_begin = begin[c];
+            e.kind = batch_kind(b, f.window);
+            e.aligned = is16(f.src) && is16(f.dst) && is16(f.src_pitch) && is16(f.dst_pitch);
+            e.pad = 0;
+            uint32_t *m = map + (size_t)c * p->max_tiles + begin[c];
+            for (int t = 0; t < nt; ++t) m[t] = (uint32_t)i;
+            begin[c] += nt;
+        }
+
+        // the kernels of this set's previous batch must be done with its tables
+        if (s.used && hipStreamWaitEvent(stream, s.done, 0) != hipSuccess) return IRF_ERR_HIP;
+        if (hipMemcpyAsync(s.dev, s.host, p->desc_off + sizeof(FrameDesc) * (size_t)n,
+                           hipMemcpyHostToDevice, stream) != hipSuccess)
+            return IRF_ERR_HIP;
+        for (int c = 0; c < 2; ++c) {
+            if (tiles[c] == 0) continue;
+            const size_t off = p->map_off + sizeof(uint32_t) * (size_t)c * p->max_tiles;
+            if (hipMemcpyAsync(s.dev + off, s.host + off, sizeof(uint32_t) * (size_t)tiles[c],
+                               hipMemcpyHostToDevice, stream) != hipSuccess)
+                return IRF_ERR_HIP;
+        }
+        if (hipEventRecord(s.copied, stream) != hipSuccess) return IRF_ERR_HIP;
+        s.used = true;
+        if (counts) {
+            hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
+                               reinterpret_cast<unsigned long long *>(counts), n);
+        }
+        if (s.graph) {
+            if (hipGraphLaunch(s.graph, stream) != hipSuccess) return IRF_ERR_HIP;
+        } else {
+            launch_batch(p, s, (tiles[0] ? 1u : 0u) | (tiles[1] ? 2u : 0u), stream);
+        }
+        if (hipEventRecord(s.done, stream) != hipSuccess) return IRF_ERR_HIP;
+        if (hipGetLastError() != hipSuccess) return IRF_ERR_HIP;
+        return IRF_OK;
+    } catch (...) {
+        return IRF_ERR_HIP;
+    }
+}
+
+void ir_filter_plan_destroy(irf_plan *p) {
+    if (!p) return;
+    for (auto &s : p->set)
+        if (s.used) (void)hipEventSynchronize(s.done);
+    free_plan(p);
+}
+
+}  // extern "C"

@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kThreads) void fnr_persistent_kernel(StackArgs a) {
     }
 }
 
-__global__ void zero_u64_kernel(unsigned long long *p, int n) {
+static __global__ void zero_u64_kernel(unsigned long long *p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
 }

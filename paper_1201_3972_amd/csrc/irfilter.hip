@@ -9,61 +9,18 @@
 
 #include "../../include/irfilter.h"
 #include "fnr_device.hpp"
+#include "host_common.hpp"
 
 namespace irf {
 namespace {
 
+using namespace host;
+
 constexpr int kVersion = (1 << 16) | 0;
-
-int bytes_of(irf_dtype d) { return d == IRF_U8 ? 1 : (d == IRF_U16 ? 2 : 0); }
-
-// One frame stack as seen by validation: [base, base + extent) must not overlap
-// another output or input.
-struct Span {
-    uintptr_t lo, hi;
-};
-
-Span span_of(const void *p, size_t pitch, size_t stride, int width, int height, int nframes,
-             int bytes) {
-    uintptr_t lo = reinterpret_cast<uintptr_t>(p);
-    uint64_t ext = (uint64_t)stride * (uint64_t)(nframes - 1) + (uint64_t)pitch * (uint64_t)(height - 1) +
-                   (uint64_t)width * (uint64_t)bytes;
-    return {lo, lo + (uintptr_t)ext};
-}
-
-bool overlap(Span a, Span b) { return a.lo < b.hi && b.lo < a.hi; }
-
-bool is16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
-bool is16(size_t v) { return (v & 15u) == 0; }
-
-irf_status check_common(int width, int height, int nframes, irf_dtype dtype, int window) {
-    if (width < 1 || height < 1 || width > IRF_MAX_DIM || height > IRF_MAX_DIM || nframes < 1)
-        return IRF_ERR_DIMS;
-    if (bytes_of(dtype) == 0) return IRF_ERR_DTYPE;
-    if (window < 3 || window > IRF_MAX_WINDOW || (window & 1) == 0) return IRF_ERR_WINDOW;
-    return IRF_OK;
-}
-
-irf_status check_layout(size_t pitch, size_t stride, int width, int height, int nframes, int bytes) {
-    if (pitch < (size_t)width * (size_t)bytes) return IRF_ERR_PITCH;
-    if (nframes > 1 && stride < pitch * (size_t)height) return IRF_ERR_PITCH;
-    return IRF_OK;
-}
 
 int tile_rows(int window) {
     (void)window;
     return kStrips * Geometry<3>::R;  // every window uses the same tile height
-}
-
-int device_cus() {
-    static const int cus = [] {
-        int dev = 0, n = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
-            n = 256;
-        return n;
-    }();
-    return cus;
 }
 
 // Persistent grid: as many workgroups as fit on the device at once (never more

@@ -38,9 +38,23 @@ SIGNATURES = {
     "ir_filter_run": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp]),
     "ir_filter_run_frames": (_i32, [_vp, _sz, _sz, _vp, _sz, _sz, _i32, _i32, _i32, _i32, _i32, _i32,
                                     _vp, _sz, _sz, _vp, _vp]),
+    "ir_filter_plan_create": (_i32, [ctypes.POINTER(ctypes.c_void_p), _i32, _i32, ctypes.c_uint]),
+    "ir_filter_run_batch": (_i32, [_vp, _vp, _i32, _vp, _vp]),
+    "ir_filter_plan_destroy": (None, [_vp]),
+    "ir_filter_frame_tiles": (_i32, [_i32, _i32]),
     "ir_filter_status_string": (ctypes.c_char_p, [_i32]),
     "ir_filter_version": (_i32, []),
 }
+
+
+IRF_PLAN_GRAPH = 1
+
+
+class IrfFrame(ctypes.Structure):
+    """Mirror of ``irf_frame``."""
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("src_pitch", ctypes.c_size_t),
+                ("dst_pitch", ctypes.c_size_t), ("width", ctypes.c_int), ("height", ctypes.c_int),
+                ("dtype", ctypes.c_int), ("window", ctypes.c_int)]
 
 
 class LibraryNotBuilt(ImportError):
@@ -181,3 +195,60 @@ def ir_filter_run_frames(src, dst, window: int, passes: int = 1, scratch=None, f
 
 def version() -> int:
     return load().ir_filter_version()
+
+
+def frame_tiles(width: int, height: int) -> int:
+    return load().ir_filter_frame_tiles(width, height)
+
+
+class Plan:
+    """Owner of an ``irf_plan``: batches of uneven frames in one persistent launch.
+
+    ``run(items)`` takes ``(src, dst, window)`` triples of 2-D CUDA tensors (each
+    frame may have its own size, pixel type and window)."""
+
+    def __init__(self, max_frames: int, max_tiles: int, graph: bool = False):
+        self._lib = load()
+        self._ptr = ctypes.c_void_p()
+        _check("ir_filter_plan_create",
+               self._lib.ir_filter_plan_create(ctypes.byref(self._ptr), max_frames, max_tiles,
+                                               IRF_PLAN_GRAPH if graph else 0))
+        self.max_frames, self.max_tiles, self.graph = max_frames, max_tiles, graph
+
+    @staticmethod
+    def frames(items) -> "ctypes.Array":
+        arr = (IrfFrame * len(items))()
+        for i, (src, dst, window) in enumerate(items):
+            _same(src, dst, "dst")
+            sp, spitch = _frame(src, "src")
+            dp, dpitch = _frame(dst, "dst")
+            H, W = src.shape
+            arr[i] = IrfFrame(sp, dp, spitch, dpitch, W, H, _dtype_code(src), window)
+        return arr
+
+    def run(self, items, flagged_counts=None, stream=None) -> None:
+        self.run_frames(self.frames(items), len(items), flagged_counts, stream)
+
+    def run_frames(self, arr, n: int, flagged_counts=None, stream=None) -> None:
+        """Run prepared ``IrfFrame`` descriptors (see :meth:`frames`)."""
+        if self._ptr is None:
+            raise RuntimeError("plan is closed")
+        cp = None if flagged_counts is None else flagged_counts.data_ptr()
+        _check("ir_filter_run_batch", self._lib.ir_filter_run_batch(self._ptr, arr, n, cp, _stream(stream)))
+
+    def close(self) -> None:
+        if self._ptr is not None and self._ptr.value:
+            self._lib.ir_filter_plan_destroy(self._ptr)
+        self._ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

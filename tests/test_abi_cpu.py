@@ -121,3 +121,21 @@ def test_frames_validation(lib):
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(irfilter.LibraryNotBuilt):
         irfilter.load(str(tmp_path / "nope.so"))
+
+
+def test_plan_argument_checks_before_any_device_call(lib):
+    import ctypes
+    ptr = ctypes.c_void_p()
+    assert lib.ir_filter_plan_create(None, 4, 4, 0) == -1
+    assert lib.ir_filter_plan_create(ctypes.byref(ptr), 0, 4, 0) == -2
+    assert lib.ir_filter_plan_create(ctypes.byref(ptr), 4, 0, 0) == -2
+    assert ptr.value is None
+    assert lib.ir_filter_run_batch(None, None, 1, None, None) == -1
+    lib.ir_filter_plan_destroy(None)  # ignored
+
+
+def test_frame_tile_count(lib):
+    assert lib.ir_filter_frame_tiles(640, 512) == 5 * 8
+    assert lib.ir_filter_frame_tiles(129, 65) == 2 * 2
+    assert lib.ir_filter_frame_tiles(1, 1) == 1
+    assert lib.ir_filter_frame_tiles(0, 5) == 0

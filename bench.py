@@ -111,6 +111,139 @@ def to_dev(torch, a, dev):
     return torch.from_numpy(a.view(np.int16)).to(dev).view(torch.uint16)
 
 
+def _timed(torch, fn, reps: int) -> float:
+    """Average milliseconds of fn() over reps, by events on the current stream."""
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def section_c1(torch, irfilter, synth, oracle, dev) -> dict:
+    """320x240 u8, 20 % salt-and-pepper, 3x3: one frame per call (latency form)."""
+    f = synth.c1_frame()
+    src = torch.from_numpy(f).to(dev)
+    dst = torch.empty_like(src)
+    irfilter.ir_filter_run(src, dst, 3)
+    torch.cuda.synchronize()
+    if not np.array_equal(dst.cpu().numpy(), oracle.fnr(f, 3)[0]):
+        raise RuntimeError("c1 parity failure")
+    ms = _timed(torch, lambda: irfilter.ir_filter_run(src, dst, 3), 200)
+    lat = []
+    for _ in range(200):
+        t1 = time.perf_counter()
+        irfilter.ir_filter_run(src, dst, 3)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    return {"workload": "320x240 u8, 20% salt-and-pepper, 3x3, one frame per call",
+            "device_ms_per_frame": round(ms, 4), "MP_per_s": round(f.size / ms / 1e3, 1),
+            "host_latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "host_latency_p99_ms": round(float(np.percentile(lat, 99)), 4)}
+
+
+def section_c3(torch, irfilter, synth, oracle, dev, frames: int = 64) -> dict:
+    """1920x1080 u16, 40 % mixed impulses, windows 3..15: a stack per window."""
+    f = synth.make_frame(synth.c3_spec())
+    src = torch.empty((frames, 1080, 1920), dtype=torch.uint16, device=dev)
+    one = to_dev(torch, f, dev)
+    for i in range(frames):
+        src[i].copy_(one)
+    dst = torch.empty_like(src)
+    out = {"workload": f"1920x1080 u16 14-bit, read noise sigma 20, 40% mixed impulses, stack of {frames}",
+           "windows": {}}
+    for k in synth.C3_WINDOWS:
+        irfilter.ir_filter_run_frames(src, dst, k)
+        torch.cuda.synchronize()
+        want = to_dev(torch, oracle.fnr(f, k)[0], dev).view(torch.int16)
+        d16 = dst.view(torch.int16)
+        if not all(torch.equal(d16[i], want) for i in (0, frames // 2, frames - 1)):
+            raise RuntimeError(f"c3 parity failure at window {k}")
+        ms = _timed(torch, lambda: irfilter.ir_filter_run_frames(src, dst, k), 5)
+        px = frames * 1920 * 1080
+        out["windows"][str(k)] = {"ms": round(ms, 3), "MP_per_s": round(px / ms / 1e3, 1),
+                                  "algorithmic_GBps": round(4 * px / ms / 1e6, 1)}
+    return out
+
+
+def section_c4(torch, irfilter, synth, oracle, dev) -> dict:
+    """256 uneven frames (160x120..1280x1024, u8/u16, windows 3/5/7/9): plain
+    per-frame launches against one persistent batched launch (with and
+    without graph replay)."""
+    items = synth.c4_items(256)
+    frames = [synth.make_frame(it.spec) for it in items]
+    srcs = [to_dev(torch, fr, dev) if fr.dtype == np.uint16 else torch.from_numpy(fr).to(dev) for fr in frames]
+    dsts = [torch.empty_like(x) for x in srcs]
+    refs = [torch.empty_like(x) for x in srcs]
+    tiles = sum(irfilter.frame_tiles(fr.shape[1], fr.shape[0]) for fr in frames)
+    px = sum(fr.size for fr in frames)
+    plan_g = irfilter.Plan(256, tiles, graph=True)
+    plan = irfilter.Plan(256, tiles, graph=False)
+    batch_items = [(a, b, it.window) for a, b, it in zip(srcs, dsts, items)]
+    arr = irfilter.Plan.frames(batch_items)
+    plan_g.run_frames(arr, len(items))
+    for a, r, it in zip(srcs, refs, items):
+        irfilter.ir_filter_run(a, r, it.window)
+    torch.cuda.synchronize()
+    for i, (d, r) in enumerate(zip(dsts, refs)):
+        if not torch.equal(d.view(torch.uint8) if d.dtype == torch.uint8 else d.view(torch.int16),
+                           r.view(torch.uint8) if r.dtype == torch.uint8 else r.view(torch.int16)):
+            raise RuntimeError(f"c4 batch differs from per-frame launch at frame {i}")
+    for i in range(0, len(items), 32):
+        got = dsts[i].view(torch.int16).cpu().numpy().view(np.uint16) if frames[i].dtype == np.uint16 \
+            else dsts[i].cpu().numpy()
+        if not np.array_equal(got, oracle.fnr(frames[i], items[i].window)[0]):
+            raise RuntimeError(f"c4 parity failure at frame {i}")
+
+    def per_frame():
+        for a, r, it in zip(srcs, refs, items):
+            irfilter.ir_filter_run(a, r, it.window)
+
+    ms_pf = _timed(torch, per_frame, 5)
+    ms_b = _timed(torch, lambda: plan.run_frames(arr, len(items)), 10)
+    ms_g = _timed(torch, lambda: plan_g.run_frames(arr, len(items)), 10)
+    plan.close()
+    plan_g.close()
+    b = sum(fr.size * fr.itemsize for fr in frames) * 2
+    return {"workload": "256 frames W~U{160..1280} x H~U{120..1024}, u8/u16, windows 3/5/7/9, "
+                        "5-60% mixed impulses", "pixels": px, "tiles": tiles,
+            "per_frame": {"ms": round(ms_pf, 3), "MP_per_s": round(px / ms_pf / 1e3, 1)},
+            "batched": {"ms": round(ms_b, 3), "MP_per_s": round(px / ms_b / 1e3, 1),
+                        "algorithmic_GBps": round(b / ms_b / 1e6, 1)},
+            "batched_graph": {"ms": round(ms_g, 3), "MP_per_s": round(px / ms_g / 1e3, 1)},
+            "batched_over_per_frame": round(ms_pf / min(ms_b, ms_g), 2)}
+
+
+def section_c5(torch, serving, dev, duration: float = 3.0) -> dict:
+    """32 video streams of 640x512 u16 at 30 fps (Poisson arrivals) plus 5 %
+    3840x2160 u16 frames, windows 3..9, served by the continuous-batching loop
+    with a bounded device-memory arena; then the same mix offered 20x faster."""
+    out = {"workload": "32 x 640x512 u16 streams at 30 fps (exponential inter-arrival) + 5% 3840x2160 u16 "
+                       "frames, windows 3/5/7/9, 512 MiB arena for one-off frames, results in pinned host memory"}
+    for name, scale, dur in (("offered_load", 1.0, duration), ("saturation_20x", 20.0, 0.5)):
+        streams, reqs = serving.video_workload(torch, seed=77, duration=dur, rate_scale=scale)
+        srv = serving.Server(memory_budget=512 << 20, max_inflight=3)
+        for st in streams:
+            srv.register_stream(st.stream_id, st.width, st.height, st.dtype)
+        for r in reqs:
+            srv.submit(r)
+        t1 = time.perf_counter()
+        srv.t0 = t1
+        srv.run_until_idle()
+        wall = time.perf_counter() - t1
+        srv.close()
+        rep = serving.summarize(reqs, wall)
+        rep["batches"] = srv.steps
+        rep["mean_batch"] = round(float(np.mean(srv.batch_sizes)), 2)
+        out[name] = rep
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +255,8 @@ def main() -> int:
     ap.add_argument("--no-per-frame", action="store_true", help="skip the per-frame launch baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--sections", default="c1,c3,c4,c5",
+                    help="extra workloads reported beside the headline (comma list, or 'none')")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the HBM traffic record from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
@@ -293,6 +428,21 @@ def main() -> int:
                          f"thread, {dt:.1f} s wall"}
         log(f"cpu oracle: {cpu}")
 
+    sections = {}
+    wanted = [x for x in args.sections.split(",") if x and x != "none"]
+    for name in wanted:
+        t1 = time.perf_counter()
+        if name == "c1":
+            sections["c1_single_frame"] = section_c1(torch, irfilter, synth, oracle, dev)
+        elif name == "c3":
+            sections["c3_window_sweep"] = section_c3(torch, irfilter, synth, oracle, dev)
+        elif name == "c4":
+            sections["c4_uneven_batch"] = section_c4(torch, irfilter, synth, oracle, dev)
+        elif name == "c5":
+            from paper_1201_3972_amd import serving
+            sections["c5_serving"] = section_c5(torch, serving, dev)
+        log(f"section {name}: {time.perf_counter() - t1:.1f}s")
+
     out = {
         "metric": METRIC, "value": round(mps, 1), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -305,6 +455,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "per_frame": per_frame,
         "latency": latency,
+        **sections,
     }
     print(json.dumps(out), flush=True)
     return 0

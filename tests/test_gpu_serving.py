@@ -1,0 +1,92 @@
+"""GPU tests of the continuous-batching server: every served result equals the
+result of the same frame filtered alone, and admission respects the memory
+budget."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_3972_amd import irfilter, serving
+from tests.gpu_helpers import say, to_host
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    irfilter.load()
+    return torch.device("cuda:0")
+
+
+def alone(dev, host_src, window):
+    src = host_src.to(dev)
+    dst = torch.empty_like(src)
+    irfilter.ir_filter_run(src, dst, window)
+    torch.cuda.synchronize()
+    return to_host(torch, dst)
+
+
+def test_results_in_the_mix_equal_results_alone(dev):
+    streams, reqs = serving.video_workload(torch, seed=5, duration=0.6, n_streams=8, frames_per_stream=2)
+    say(f"case serving mix: {len(reqs)} requests")
+    srv = serving.Server(memory_budget=160 << 20, max_inflight=3)
+    for s in streams:
+        srv.register_stream(s.stream_id, s.width, s.height, s.dtype)
+    for r in reqs:
+        srv.submit(r)
+    srv.run_until_idle()
+    srv.close()
+    assert len(srv.completed) == len(reqs)
+    assert max(srv.batch_sizes) > 1  # requests were batched together
+    cache = {}
+    for r in reqs:
+        key = (r.host_src.data_ptr(), r.window)
+        if key not in cache:
+            cache[key] = alone(dev, r.host_src, r.window)
+        assert np.array_equal(to_host(torch, r.host_dst), cache[key]), r.rid
+        assert r.latency is not None and r.latency >= 0
+    # the video frames also against the oracle (one per distinct frame and window)
+    seen = set()
+    for r in reqs:
+        key = (r.host_src.data_ptr(), r.window)
+        if r.stream_id is not None and key not in seen:
+            seen.add(key)
+            want, _ = oracle.fnr(to_host(torch, r.host_src), r.window)
+            assert np.array_equal(to_host(torch, r.host_dst), want)
+
+
+def test_memory_budget_serialises_large_frames(dev):
+    _, reqs = serving.video_workload(torch, seed=9, duration=0.3, n_streams=2, large_fraction=0.5,
+                                     frames_per_stream=1)
+    large = [r for r in reqs if r.stream_id is None]
+    assert len(large) >= 2
+    nb = serving.frame_bytes(3840, 2160, "u16")
+    # room for one large frame (input + output) and nothing else: one-off
+    # frames go through the arena one at a time
+    srv = serving.Server(memory_budget=2 * serving._round(nb), max_inflight=3)
+    for r in reqs:
+        srv.submit(r)
+    srv.run_until_idle()
+    srv.close()
+    assert len(srv.completed) == len(reqs)
+    assert srv.arena.used == 0
+    ref = {}
+    for r in large:
+        key = (r.host_src.data_ptr(), r.window)
+        if key not in ref:
+            ref[key] = alone(dev, r.host_src, r.window)
+        assert np.array_equal(to_host(torch, r.host_dst), ref[key])
+
+
+def test_request_larger_than_budget_is_reported(dev):
+    _, reqs = serving.video_workload(torch, seed=3, duration=0.2, n_streams=1, large_fraction=0.5,
+                                     frames_per_stream=1)
+    srv = serving.Server(memory_budget=1 << 20, max_inflight=2)
+    for r in reqs:
+        srv.submit(r)
+    with pytest.raises(RuntimeError):
+        srv.run_until_idle()
+    srv.close()

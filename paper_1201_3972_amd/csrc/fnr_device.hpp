@@ -20,11 +20,12 @@
 //               columns (two pixels per VGPR), then a van Herk / Gil-Werman
 //               sliding min/max down the R+k-1 rows;
 //   3. compact: flagged pixels of the tile go to an LDS list (wave prefix scan);
-//   4. select:  each lane takes two list entries and computes both medians in
-//               packed u16 registers: k <= 9 by forgetful selection over sorted
-//               blocks merged into a sorted run whose provably-non-median ends
-//               are dropped, k >= 11 by a bisection on grey level that counts the
-//               window values at or below the probe (bit-by-bit value search);
+//   4. select:  k <= 11: each lane takes two list entries and computes both
+//               medians in packed u16 registers by forgetful selection over
+//               sorted blocks merged into a sorted run whose provably-non-median
+//               ends are dropped; k >= 13: each lane holds one window in
+//               registers (two values per VGPR) and bisects on grey level,
+//               counting the values above the probe (bit-by-bit value search);
 //   5. store:   results replace the flagged pixels in LDS, then the tile is
 //               written out with vector stores.
 #pragma once
@@ -247,8 +248,8 @@ __device__ __forceinline__ int bit_row(int b) { return b & 7; }
 // and every output row is turned into flag bits as soon as both parts exist, so
 // only about one block of horizontal results is live at a time.
 template <int K>
-__device__ __forceinline__ uint32_t detect_block(const uint16_t *tile, int strip, int tx,
-                                                 uint32_t pk_one) {
+__device__ __forceinline__ uint32_t detect_block_blocks(const uint16_t *tile, int strip, int tx,
+                                                        uint32_t pk_one) {
     using G = Geometry<K>;
     constexpr int R = G::R, L = R + K - 1;
     const uint16_t *base = tile + strip * R * kLdsPitch + kHalo + 4 * tx;
@@ -298,6 +299,84 @@ __device__ __forceinline__ uint32_t detect_block(const uint16_t *tile, int strip
         }
     });
     return flags;
+}
+
+// The same flags for windows taller than the thread's block (K > R): rows
+// [R-1, K) lie in every output row's window (the core, reduced as it streams
+// by); output row o also needs the suffix of rows [o, R-1) and the prefix of
+// rows [K, o+K).  Only the R-1 rows before the core are held.
+template <int K>
+__device__ __forceinline__ uint32_t detect_block_core(const uint16_t *tile, int strip, int tx,
+                                                      uint32_t pk_one) {
+    using G = Geometry<K>;
+    constexpr int R = G::R, L = R + K - 1, A = R - 1;
+    static_assert(K > R && A > 0, "core split needs windows taller than the block");
+    const uint16_t *base = tile + strip * R * kLdsPitch + kHalo + 4 * tx;
+    uint32_t mn0[A], mn1[A], mx0[A], mx1[A];          // rows before the core, then suffixes
+    uint32_t cmn0 = 0, cmn1 = 0, cmx0 = 0, cmx1 = 0;  // core
+    uint32_t pmn0 = 0, pmn1 = 0, pmx0 = 0, pmx1 = 0;  // prefix of the rows after the core
+    uint32_t c0[R], c1[R];
+    uint32_t flags = 0;
+    auto emit = [&](int o, uint32_t vmn0, uint32_t vmn1, uint32_t vmx0, uint32_t vmx1) {
+        const uint32_t z0 = pk_min(pk_subsat(c0[o], vmn0), pk_subsat(vmx0, c0[o]));
+        const uint32_t z1 = pk_min(pk_subsat(c1[o], vmn1), pk_subsat(vmx1, c1[o]));
+        const uint32_t f0 = pk_subsat(pk_one, z0);
+        const uint32_t f1 = pk_subsat(pk_one, z1);
+        flags |= (f0 | (f1 << 8)) << o;
+    };
+    static_for(std::make_integer_sequence<int, L>{}, [&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        uint32_t a0, a1, b0, b1, ca, cb;
+        row_minmax<G::r>(base + i * kLdsPitch, a0, a1, b0, b1, ca, cb);
+        if constexpr (i >= G::r && i < G::r + R) {
+            c0[i - G::r] = ca;
+            c1[i - G::r] = cb;
+        }
+        if constexpr (i < A) {
+            mn0[i] = a0; mn1[i] = a1; mx0[i] = b0; mx1[i] = b1;
+        } else if constexpr (i < K) {
+            if constexpr (i == A) {
+                cmn0 = a0; cmn1 = a1; cmx0 = b0; cmx1 = b1;
+            } else {
+                cmn0 = pk_min(cmn0, a0); cmn1 = pk_min(cmn1, a1);
+                cmx0 = pk_max(cmx0, b0); cmx1 = pk_max(cmx1, b1);
+            }
+            if constexpr (i == K - 1) {
+                // suffixes of the rows before the core, each folded with the core
+                mn0[A - 1] = pk_min(mn0[A - 1], cmn0); mn1[A - 1] = pk_min(mn1[A - 1], cmn1);
+                mx0[A - 1] = pk_max(mx0[A - 1], cmx0); mx1[A - 1] = pk_max(mx1[A - 1], cmx1);
+                static_for(std::make_integer_sequence<int, A - 1>{}, [&](auto jc) {
+                    constexpr int j = A - 2 - decltype(jc)::value;
+                    mn0[j] = pk_min(mn0[j], mn0[j + 1]); mn1[j] = pk_min(mn1[j], mn1[j + 1]);
+                    mx0[j] = pk_max(mx0[j], mx0[j + 1]); mx1[j] = pk_max(mx1[j], mx1[j + 1]);
+                });
+                emit(0, mn0[0], mn1[0], mx0[0], mx1[0]);
+            }
+        } else {
+            if constexpr (i == K) {
+                pmn0 = a0; pmn1 = a1; pmx0 = b0; pmx1 = b1;
+            } else {
+                pmn0 = pk_min(pmn0, a0); pmn1 = pk_min(pmn1, a1);
+                pmx0 = pk_max(pmx0, b0); pmx1 = pk_max(pmx1, b1);
+            }
+            constexpr int o = i - K + 1;  // rows [o, o+K) are now all seen
+            if constexpr (o < A)
+                emit(o, pk_min(mn0[o], pmn0), pk_min(mn1[o], pmn1), pk_max(mx0[o], pmx0),
+                     pk_max(mx1[o], pmx1));
+            else
+                emit(o, pk_min(cmn0, pmn0), pk_min(cmn1, pmn1), pk_max(cmx0, pmx0), pk_max(cmx1, pmx1));
+        }
+    });
+    return flags;
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t detect_block(const uint16_t *tile, int strip, int tx,
+                                                 uint32_t pk_one) {
+    if constexpr (K > Geometry<K>::R)
+        return detect_block_core<K>(tile, strip, tx, pk_one);
+    else
+        return detect_block_blocks<K>(tile, strip, tx, pk_one);
 }
 
 // Bits of the thread's block that lie inside the frame.
@@ -419,47 +498,54 @@ __device__ __forceinline__ uint32_t median_blocks(const uint16_t *w0, const uint
     return select_blocks<K, 0, 0, (K * K - 1) / 2>(nullptr, w0, w1);
 }
 
-// Bisection on grey level: the median is the smallest value t with more than
-// (n-1)/2 window values <= t.  Works on [g_min, g_max] of each window, two
-// windows per lane; count of values above t uses saturating subtraction.
-template <int K>
-__device__ __forceinline__ uint32_t median_bisect(const uint16_t *w0, const uint16_t *w1) {
-    constexpr int N = K * K;
-    constexpr uint32_t rank = (N - 1) / 2;
-    uint32_t mn = 0xffffffffu, mx = 0u;
-    for (int i = 0; i < N; ++i) {
-        uint32_t v = win_pair<K>(w0, w1, i);
-        mn = pk_min(mn, v);
-        mx = pk_max(mx, v);
-    }
-    uint32_t lo0 = mn & 0xffffu, lo1 = mn >> 16, hi0 = mx & 0xffffu, hi1 = mx >> 16;
-    while (lo0 < hi0 || lo1 < hi1) {
-        uint32_t t0 = (lo0 + hi0) >> 1, t1 = (lo1 + hi1) >> 1;
-        uint32_t t = t0 | (t1 << 16);
-        uint32_t above = 0;  // packed count of values > t
-        for (int i = 0; i < N; ++i) {
-            uint32_t v = win_pair<K>(w0, w1, i);
-            above = pk_add(above, pk_min(pk_subsat(v, t), 0x00010001u));
-        }
-        uint32_t le0 = N - (above & 0xffffu), le1 = N - (above >> 16);
-        if (lo0 < hi0) {
-            if (le0 > rank) hi0 = t0;
-            else lo0 = t0 + 1;
-        }
-        if (lo1 < hi1) {
-            if (le1 > rank) hi1 = t1;
-            else lo1 = t1 + 1;
-        }
-    }
-    return lo0 | (lo1 << 16);
-}
-
 template <int K>
 __device__ __forceinline__ uint32_t median_pair(const uint16_t *w0, const uint16_t *w1) {
-    if constexpr (K <= 9)
-        return median_blocks<K>(w0, w1);
-    else
-        return median_bisect<K>(w0, w1);
+    static_assert(K <= 11, "larger windows select one window per lane in registers");
+    return median_blocks<K>(w0, w1);
+}
+
+constexpr int kRegisterSelectMin = 13;
+
+// Windows of 13x13 and 15x15, one window per lane held in registers, two
+// window values per VGPR: a bisection on grey level over [g_min, g_max] counts
+// the values above the probe with three packed operations per register and
+// round (the window is read from LDS once).
+template <int K>
+__device__ __forceinline__ uint32_t median_registers(const uint16_t *w) {
+    constexpr int N = K * K, NP = (N + 1) / 2;
+    constexpr uint32_t rank = (N - 1) / 2;
+    uint32_t v[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const int e0 = 2 * j, e1 = 2 * j + 1;
+        const uint32_t lo = w[(e0 / K) * kLdsPitch + e0 % K];
+        // an odd element count leaves the last high half empty: it repeats the
+        // last element, whose second copy is taken out of the count below
+        const uint32_t hi = e1 < N ? w[(e1 / K) * kLdsPitch + e1 % K] : lo;
+        v[j] = lo | (hi << 16);
+    }
+    uint32_t mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        mn = pk_min(mn, v[j]);
+        mx = pk_max(mx, v[j]);
+    }
+    uint32_t lo = min(mn & 0xffffu, mn >> 16), hi = max(mx & 0xffffu, mx >> 16);
+    const uint32_t pad = (N & 1) ? (v[NP - 1] >> 16) : 0u;  // duplicated value (odd N)
+    while (lo < hi) {
+        const uint32_t t = (lo + hi) >> 1;
+        const uint32_t tt = t | (t << 16);
+        uint32_t above = 0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) above = pk_add(above, pk_min(pk_subsat(v[j], tt), 0x00010001u));
+        uint32_t gt = (above & 0xffffu) + (above >> 16);
+        if ((N & 1) && pad > t) gt -= 1;
+        if (N - gt > rank)
+            hi = t;
+        else
+            lo = t + 1;
+    }
+    return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -620,13 +706,22 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         //    that as few waves as possible run the selection; which wave starts
         //    the list rotates with the tile (waves sit on fixed SIMDs)
         constexpr int corner = G::r * kLdsPitch + G::r;
-        const uint32_t slot = (uint32_t)(tid + 64 * (tile & 3)) % kThreads;
-        for (uint32_t i = 2 * slot; i < total; i += 2 * kThreads) {
-            const uint32_t e0 = sm.list[i];
-            const uint32_t e1 = (i + 1 < total) ? sm.list[i + 1] : e0;
-            const uint32_t med = median_pair<K>(sm.tile + e0 - corner, sm.tile + e1 - corner);
-            sm.list[i] = (uint16_t)(med & 0xffffu);
-            if (i + 1 < total) sm.list[i + 1] = (uint16_t)(med >> 16);
+        if constexpr (K >= kRegisterSelectMin) {
+            // one window per lane
+            const uint32_t slot = (uint32_t)(tid + 64 * (tile & 3)) % kThreads;
+            for (uint32_t i = slot; i < total; i += kThreads) {
+                const uint32_t e0 = sm.list[i];
+                sm.list[i] = (uint16_t)median_registers<K>(sm.tile + e0 - corner);
+            }
+        } else {
+            const uint32_t slot = (uint32_t)(tid + 64 * (tile & 3)) % kThreads;
+            for (uint32_t i = 2 * slot; i < total; i += 2 * kThreads) {
+                const uint32_t e0 = sm.list[i];
+                const uint32_t e1 = (i + 1 < total) ? sm.list[i + 1] : e0;
+                const uint32_t med = median_pair<K>(sm.tile + e0 - corner, sm.tile + e1 - corner);
+                sm.list[i] = (uint16_t)(med & 0xffffu);
+                if (i + 1 < total) sm.list[i + 1] = (uint16_t)(med >> 16);
+            }
         }
         __syncthreads();
         // results back into the tile at the thread's own pixels

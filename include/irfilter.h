@@ -126,8 +126,9 @@ irf_status ir_filter_run_frames(const void *src, size_t src_pitch, size_t src_st
  * irf_frame describes one frame: device src/dst, pitches, size, pixel type and
  * window; frames of a batch are independent and may all differ.  Every frame
  * is filtered once with the FNR filter (same result as ir_filter_run with
- * passes = 1).  Frames with windows 3..9 share one persistent kernel; frames
- * with windows 11..15 share a second one, launched after it on the same stream.
+ * passes = 1).  Frames with windows 3..7 share one persistent kernel, frames
+ * with windows 9..11 a second and frames with windows 13..15 a third, launched
+ * one after the other on the same stream.
  */
 typedef struct {
     const void *src;

@@ -19,7 +19,8 @@ using namespace irf::host;
 namespace {
 
 constexpr int kSets = 2;          // device table sets used alternately
-constexpr size_t kQueueBytes = 64;  // two BatchQueue records
+constexpr size_t kQueueBytes = 64;  // one BatchQueue record per class, padded
+static_assert(kBatchClasses * sizeof(BatchQueue) <= kQueueBytes, "queue records overflow");
 
 int frame_tiles(int width, int height) {
     const int th = kStrips * Geometry<3>::R;
@@ -46,7 +47,7 @@ struct irf_plan {
     int max_frames = 0, max_tiles = 0;
     unsigned flags = 0;
     size_t desc_off = 0, map_off = 0, bytes = 0;
-    int grid[2] = {0, 0};
+    int grid[kBatchClasses] = {};
     int next_set = 0;
     struct Set {
         unsigned char *dev = nullptr;
@@ -61,19 +62,23 @@ struct irf_plan {
 namespace {
 
 // Each window class has its own queue and its own region of the tile map
-// (class c at map + c * max_tiles), so the arguments of both kernels are fixed
+// (class c at map + c * max_tiles), so the arguments of every kernel are fixed
 // per table set and can be captured in a graph once.  `classes` selects the
 // kernels (bit c = class c).
-void launch_batch(const irf_plan *p, const irf_plan::Set &s, unsigned classes, hipStream_t stream) {
+template <int CLASS>
+void launch_class(const irf_plan *p, const irf_plan::Set &s, hipStream_t stream) {
     BatchQueue *q = reinterpret_cast<BatchQueue *>(s.dev);
     const FrameDesc *d = reinterpret_cast<const FrameDesc *>(s.dev + p->desc_off);
     const uint32_t *map = reinterpret_cast<const uint32_t *>(s.dev + p->map_off);
-    if (classes & 1u)
-        hipLaunchKernelGGL(fnr_batch_kernel<0>, dim3(p->grid[0]), dim3(kThreads), 0, stream, d, map, q,
-                           0x00010001u);
-    if (classes & 2u)
-        hipLaunchKernelGGL(fnr_batch_kernel<1>, dim3(p->grid[1]), dim3(kThreads), 0, stream, d,
-                           map + p->max_tiles, q + 1, 0x00010001u);
+    hipLaunchKernelGGL(fnr_batch_kernel<CLASS>, dim3(p->grid[CLASS]), dim3(kThreads), 0, stream, d,
+                       map + (size_t)CLASS * p->max_tiles, q + CLASS, 0x00010001u);
+}
+
+void launch_batch(const irf_plan *p, const irf_plan::Set &s, unsigned classes, hipStream_t stream) {
+    static_assert(kBatchClasses == 3, "one launch per class");
+    if (classes & 1u) launch_class<0>(p, s, stream);
+    if (classes & 2u) launch_class<1>(p, s, stream);
+    if (classes & 4u) launch_class<2>(p, s, stream);
 }
 
 void free_plan(irf_plan *p) {
@@ -135,10 +140,11 @@ irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles,
         p->flags = flags;
         p->desc_off = kQueueBytes;
         p->map_off = p->desc_off + sizeof(FrameDesc) * (size_t)max_frames;
-        p->bytes = p->map_off + sizeof(uint32_t) * 2 * (size_t)max_tiles;
+        p->bytes = p->map_off + sizeof(uint32_t) * kBatchClasses * (size_t)max_tiles;
         (void)hipGetLastError();
         p->grid[0] = batch_grid<0>();
         p->grid[1] = batch_grid<1>();
+        p->grid[2] = batch_grid<2>();
         for (auto &s : p->set) {
             if (hipMalloc(&s.dev, p->bytes) != hipSuccess) {
                 free_plan(p);
@@ -168,7 +174,7 @@ irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles,
             for (auto &s : p->set) {
                 hipGraph_t g = nullptr;
                 ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-                if (ok) launch_batch(p, s, 3u, cs);
+                if (ok) launch_batch(p, s, (1u << kBatchClasses) - 1, cs);
                 ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok;
                 ok = ok && hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0) == hipSuccess;
                 if (g) (void)hipGraphDestroy(g);
@@ -195,7 +201,7 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         if (!p || !frames) return IRF_ERR_NULL;
         if (n < 1) return IRF_ERR_DIMS;
         if (n > p->max_frames) return IRF_ERR_CAPACITY;
-        long long tiles[2] = {0, 0};
+        long long tiles[kBatchClasses] = {};
         for (int i = 0; i < n; ++i) {
             const irf_frame &f = frames[i];
             if (!f.src || !f.dst) return IRF_ERR_NULL;
@@ -206,7 +212,8 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
             if ((st = check_layout(f.dst_pitch, 0, f.width, f.height, 1, b))) return st;
             tiles[batch_class(f.window)] += frame_tiles(f.width, f.height);
         }
-        if (tiles[0] > p->max_tiles || tiles[1] > p->max_tiles) return IRF_ERR_CAPACITY;
+        for (int c = 0; c < kBatchClasses; ++c)
+            if (tiles[c] > p->max_tiles) return IRF_ERR_CAPACITY;
         if (batch_aliases(frames, n)) return IRF_ERR_ALIAS;
         if (counts) {
             const Span cs = {reinterpret_cast<uintptr_t>(counts),
@@ -226,14 +233,13 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         p->next_set = (p->next_set + 1) % kSets;
         if (s.used && hipEventSynchronize(s.copied) != hipSuccess) return IRF_ERR_HIP;
 
-        // host staging: queues, descriptors, tile map (class 0 region, then class 1)
+        // host staging: queues, descriptors, tile map (one region per class)
         BatchQueue *q = reinterpret_cast<BatchQueue *>(s.host);
         FrameDesc *d = reinterpret_cast<FrameDesc *>(s.host + p->desc_off);
         uint32_t *map = reinterpret_cast<uint32_t *>(s.host + p->map_off);
         memset(q, 0, kQueueBytes);
-        q[0].total = (unsigned)tiles[0];
-        q[1].total = (unsigned)tiles[1];
-        int begin[2] = {0, 0};
+        for (int c = 0; c < kBatchClasses; ++c) q[c].total = (unsigned)tiles[c];
+        int begin[kBatchClasses] = {};
         for (int i = 0; i < n; ++i) {
             const irf_frame &f = frames[i];
             const int b = bytes_of(f.dtype), c = batch_class(f.window), nt = frame_tiles(f.width, f.height);
@@ -261,7 +267,7 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         if (hipMemcpyAsync(s.dev, s.host, p->desc_off + sizeof(FrameDesc) * (size_t)n,
                            hipMemcpyHostToDevice, stream) != hipSuccess)
             return IRF_ERR_HIP;
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < kBatchClasses; ++c) {
             if (tiles[c] == 0) continue;
             const size_t off = p->map_off + sizeof(uint32_t) * (size_t)c * p->max_tiles;
             if (hipMemcpyAsync(s.dev + off, s.host + off, sizeof(uint32_t) * (size_t)tiles[c],
@@ -277,7 +283,10 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         if (s.graph) {
             if (hipGraphLaunch(s.graph, stream) != hipSuccess) return IRF_ERR_HIP;
         } else {
-            launch_batch(p, s, (tiles[0] ? 1u : 0u) | (tiles[1] ? 2u : 0u), stream);
+            unsigned classes = 0;
+            for (int c = 0; c < kBatchClasses; ++c)
+                if (tiles[c]) classes |= 1u << c;
+            launch_batch(p, s, classes, stream);
         }
         if (hipEventRecord(s.done, stream) != hipSuccess) return IRF_ERR_HIP;
         if (hipGetLastError() != hipSuccess) return IRF_ERR_HIP;

@@ -34,18 +34,21 @@ struct BatchQueue {
     unsigned int pad[2];
 };
 
-// Window classes: one kernel for 3..9 (LDS and registers sized for 9x9), one
-// for 11..15.
-constexpr int kBatchClassMax[2] = {9, 15};
-// Occupancy targets: every window's code sits in one kernel, whose register
-// count is the worst case over them; these targets keep the 3..9 kernel at 4
-// waves per SIMD (as the per-window kernels) without spilling.
-constexpr int kBatchClassWaves[2] = {4, 3};
+// Window classes, one kernel each: 3..7, 9..11 and 13..15 (LDS and registers
+// sized for the class's largest window).
+constexpr int kBatchClasses = 3;
+constexpr int kBatchClassMax[kBatchClasses] = {7, 11, 15};
+// Occupancy targets: every window's code sits in its class's kernel, whose
+// register count is the worst case over them; these targets keep each kernel at
+// the occupancy of its largest window's own kernel without spilling.
+constexpr int kBatchClassWaves[kBatchClasses] = {4, 3, 2};
 
 __host__ __device__ constexpr int batch_kind(int bytes, int window) {
     return (bytes == 1 ? 0 : 8) + (window - 3) / 2;
 }
-__host__ __device__ constexpr int batch_class(int window) { return window <= 9 ? 0 : 1; }
+__host__ __device__ constexpr int batch_class(int window) {
+    return window <= kBatchClassMax[0] ? 0 : (window <= kBatchClassMax[1] ? 1 : 2);
+}
 
 template <typename T, int K>
 __device__ __forceinline__ uint32_t batch_tile(const FrameDesc &d, int local, unsigned char *smem,
@@ -101,18 +104,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kBatch
                 case batch_kind(1, 3): flagged = batch_tile<uint8_t, 3>(d, local, smem, ticket, slot, pk_one); break;
                 case batch_kind(1, 5): flagged = batch_tile<uint8_t, 5>(d, local, smem, ticket, slot, pk_one); break;
                 case batch_kind(1, 7): flagged = batch_tile<uint8_t, 7>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 9): flagged = batch_tile<uint8_t, 9>(d, local, smem, ticket, slot, pk_one); break;
                 case batch_kind(2, 3): flagged = batch_tile<uint16_t, 3>(d, local, smem, ticket, slot, pk_one); break;
                 case batch_kind(2, 5): flagged = batch_tile<uint16_t, 5>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 7): flagged = batch_tile<uint16_t, 7>(d, local, smem, ticket, slot, pk_one); break;
-                default: flagged = batch_tile<uint16_t, 9>(d, local, smem, ticket, slot, pk_one); break;
+                default: flagged = batch_tile<uint16_t, 7>(d, local, smem, ticket, slot, pk_one); break;
+            }
+        } else if constexpr (CLASS == 1) {
+            switch (d.kind) {
+                case batch_kind(1, 9): flagged = batch_tile<uint8_t, 9>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(1, 11): flagged = batch_tile<uint8_t, 11>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(2, 9): flagged = batch_tile<uint16_t, 9>(d, local, smem, ticket, slot, pk_one); break;
+                default: flagged = batch_tile<uint16_t, 11>(d, local, smem, ticket, slot, pk_one); break;
             }
         } else {
             switch (d.kind) {
-                case batch_kind(1, 11): flagged = batch_tile<uint8_t, 11>(d, local, smem, ticket, slot, pk_one); break;
                 case batch_kind(1, 13): flagged = batch_tile<uint8_t, 13>(d, local, smem, ticket, slot, pk_one); break;
                 case batch_kind(1, 15): flagged = batch_tile<uint8_t, 15>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 11): flagged = batch_tile<uint16_t, 11>(d, local, smem, ticket, slot, pk_one); break;
                 case batch_kind(2, 13): flagged = batch_tile<uint16_t, 13>(d, local, smem, ticket, slot, pk_one); break;
                 default: flagged = batch_tile<uint16_t, 15>(d, local, smem, ticket, slot, pk_one); break;
             }

@@ -9,12 +9,11 @@
 //     (Section 3.4); the frame may be filtered several times (Section 4).
 // Border windows replicate the edge pixels; each pass reads an unchanged input.
 //
-// A persistent workgroup of 256 threads walks a range of tiles of kTileW x (8*R)
-// output pixels.  Each tile and an r-pixel halo (rounded out to 8 columns) are
-// staged in LDS as 16-bit values, whatever the pixel type.  The steps:
+// A persistent workgroup of 128 threads (two waves) walks a range of tiles of
+// kTileW x (4*R) output pixels.  Each tile and an r-pixel halo (rounded out to
+// 8 columns) are staged in LDS as 16-bit values, whatever the pixel type.  The
+// steps:
 //   1. load:    coalesced 8-pixel chunks, rows and columns clamped at the border;
-//               the next tile's loads are issued into registers before the
-//               current tile is processed, so HBM reads overlap the compute;
 //   2. detect:  every thread owns 4 columns x R rows; window min and max are
 //               separable: per input row a packed-u16 horizontal min/max over k
 //               columns (two pixels per VGPR), then a van Herk / Gil-Werman
@@ -23,9 +22,10 @@
 //   4. select:  k <= 11: each lane takes two list entries and computes both
 //               medians in packed u16 registers by forgetful selection over
 //               sorted blocks merged into a sorted run whose provably-non-median
-//               ends are dropped; k >= 13: each lane holds one window in
-//               registers (two values per VGPR) and bisects on grey level,
-//               counting the values above the probe (bit-by-bit value search);
+//               ends are dropped (window rows are read as whole 32-bit words);
+//               k >= 13: each lane holds one window in registers (two values
+//               per VGPR) and bisects on grey level, counting the values above
+//               the probe (bit-by-bit value search);
 //   5. store:   results replace the flagged pixels in LDS, then the tile is
 //               written out with vector stores.
 #pragma once
@@ -39,10 +39,10 @@
 
 namespace irf {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 128;
 constexpr int kTileW = 128;                  // output columns per tile
 constexpr int kThreadsX = kTileW / 4;        // 32 threads across, 4 columns each
-constexpr int kStrips = kThreads / kThreadsX;  // 8 strips of R rows
+constexpr int kStrips = kThreads / kThreadsX;  // 4 strips of R rows
 constexpr int kHalo = 8;                     // LDS columns kept left and right of the tile
 constexpr int kLdsW = kTileW + 2 * kHalo;    // 144 16-bit values staged per LDS row
 constexpr int kChunks = kLdsW / 8;           // 8-pixel load chunks per LDS row
@@ -169,6 +169,8 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
                                           int y0, bool aligned, uint16_t *tile) {
     using G = Geometry<K>;
     uint4 v[G::per_thread];
+    // columns of the whole staged tile inside the frame: no per-chunk checks
+    const bool interior = aligned && x0 >= kHalo && x0 + kTileW + kHalo <= W;
 #pragma unroll
     for (int i = 0; i < G::per_thread; ++i) {
         const int idx = threadIdx.x + i * kThreads;
@@ -176,7 +178,16 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
             const int row = idx / kChunks;
             const int c = idx - row * kChunks;
             const int gy = min(max(y0 - G::r + row, 0), H - 1);
-            v[i] = load_chunk<T>(src + (uint64_t)gy * pitch, x0 - kHalo + 8 * c, W, aligned);
+            const uint8_t *rp = src + (uint64_t)gy * pitch;
+            const int gx = x0 - kHalo + 8 * c;
+            if (interior) {
+                if constexpr (sizeof(T) == 2)
+                    v[i] = *reinterpret_cast<const uint4 *>(rp + 2 * (uint64_t)gx);
+                else
+                    v[i] = widen8(*reinterpret_cast<const uint2 *>(rp + gx));
+            } else {
+                v[i] = load_chunk<T>(rp, gx, W, aligned);
+            }
         }
     }
 #pragma unroll
@@ -394,16 +405,6 @@ __device__ __forceinline__ uint32_t valid_bits(int R, int W, int H, int px, int 
 // ---------------------------------------------------------------------------
 // 4. median selection on two windows at once (packed u16)
 // ---------------------------------------------------------------------------
-// Window element i (row-major) of the window whose top-left LDS value is w.
-template <int K>
-__device__ __forceinline__ uint32_t win_pair(const uint16_t *w0, const uint16_t *w1, int i) {
-    const int off = (i / K) * kLdsPitch + (i % K);
-    u16x2 v;  // element-wise build lets the compiler load straight into each half
-    v.x = w0[off];
-    v.y = w1[off];
-    return __builtin_bit_cast(uint32_t, v);
-}
-
 template <int... I, typename F>
 __device__ __forceinline__ void static_for(std::integer_sequence<int, I...>, F &&f) {
     (f(std::integral_constant<int, I>{}), ...);
@@ -456,6 +457,64 @@ struct BlockPlan {
     static constexpr int max_run = 64;
 };
 
+// One row of two K x K windows, packed: out[i] holds a value of window 0 in its
+// low half and one of window 1 in its high half.  q0 and q1 point at the 32-bit
+// LDS words holding the rows' first values, p0 and p1 are the parities of the
+// rows' first columns.  A row is read as the (K+1)/2 whole words that cover it,
+// so no LDS access straddles a word: with even parity the row runs from the low
+// half of word 0 to the low half of word K/2, with odd parity from the high
+// half of word 0 to the high half of word K/2.  Only that one value differs
+// between the parities; the values come out in a fixed order that is not the
+// column order, which the median ignores.
+// 3 x 3 rows are read value by value instead (three 16-bit reads per window and
+// row cost less than the word reads and the byte permutes).
+struct PairRow {
+    const uint16_t *w0, *w1;  // first values of the windows' top rows
+    const uint32_t *q0, *q1;  // the words holding them
+    uint32_t s0, s1;          // byte selectors of the parity-dependent values
+};
+
+__device__ __forceinline__ PairRow pair_row(const uint16_t *tile, uint32_t o0, uint32_t o1) {
+    const uint32_t *t32 = reinterpret_cast<const uint32_t *>(tile);
+    // the parity-dependent value of window 0 goes to bytes 0-1, that of window 1
+    // to bytes 2-3 (source bytes 0-3 = word 0, 4-7 = word K/2)
+    return {tile + o0, tile + o1, t32 + (o0 >> 1), t32 + (o1 >> 1), 0x0100u + (o0 & 1) * 0x0606u,
+            (0x0100u + (o1 & 1) * 0x0606u) << 16};
+}
+
+template <int K>
+__device__ __forceinline__ void load_pair_row(const PairRow &w, int row, uint32_t *out) {
+    if constexpr (K == 3) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            u16x2 v;  // element-wise build lets the compiler load straight into each half
+            v.x = w.w0[row * kLdsPitch + i];
+            v.y = w.w1[row * kLdsPitch + i];
+            out[i] = __builtin_bit_cast(uint32_t, v);
+        }
+        return;
+    }
+    constexpr int D = (K + 1) / 2;
+    constexpr uint32_t kLoLo = 0x05040100u, kHiHi = 0x07060302u, kLoHi = 0x07060100u;
+    uint32_t a[D], b[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        a[j] = w.q0[row * (kLdsPitch / 2) + j];
+        b[j] = w.q1[row * (kLdsPitch / 2) + j];
+    }
+    int n = 0;
+    out[n++] = __builtin_amdgcn_perm(b[0], a[0], kHiHi);
+#pragma unroll
+    for (int j = 1; j < D - 1; ++j) {
+        out[n++] = __builtin_amdgcn_perm(b[j], a[j], kLoLo);
+        out[n++] = __builtin_amdgcn_perm(b[j], a[j], kHiHi);
+    }
+    out[n++] = __builtin_amdgcn_perm(b[D - 1], a[D - 1], kLoLo);
+    const uint32_t x0 = __builtin_amdgcn_perm(a[D - 1], a[0], w.s0);
+    const uint32_t x1 = __builtin_amdgcn_perm(b[D - 1], b[0], w.s1);
+    out[n++] = __builtin_amdgcn_perm(x1, x0, kLoHi);
+}
+
 // Forgetful selection over sorted blocks.  State: a sorted run of L values, the
 // rank T (0-based) that the median has among the run plus the N-POS values not
 // yet read.  Each step sorts the next block, merges it into the run and drops
@@ -464,8 +523,7 @@ struct BlockPlan {
 // (more than T run values lie below them).  When every value has been read the
 // run holds exactly one value, the median.
 template <int K, int POS, int L, int T>
-__device__ __forceinline__ uint32_t select_blocks(const uint32_t *run, const uint16_t *w0,
-                                                  const uint16_t *w1) {
+__device__ __forceinline__ uint32_t select_blocks(const uint32_t *run, const PairRow &w, uint32_t *win) {
     constexpr int N = K * K;
     if constexpr (POS == N) {
         static_assert(L == 1, "forgetful selection must end with one value");
@@ -478,9 +536,12 @@ __device__ __forceinline__ uint32_t select_blocks(const uint32_t *run, const uin
         constexpr int DHIGH = M - 1 - T > 0 ? M - 1 - T : 0;
         constexpr int NL = M - DLOW - DHIGH;
         static_assert(M <= 2 * BlockPlan<K>::max_run, "run too long");
+        // rows are read when the block that reaches their first value starts
+#pragma unroll
+        for (int row = (POS + K - 1) / K; row * K < POS + S; ++row) load_pair_row<K>(w, row, win + row * K);
         uint32_t blk[S];
 #pragma unroll
-        for (int i = 0; i < S; ++i) blk[i] = win_pair<K>(w0, w1, POS + i);
+        for (int i = 0; i < S; ++i) blk[i] = win[POS + i];
         sort_block<S>(blk);
         uint32_t merged[M];
         if constexpr (L == 0) {
@@ -489,19 +550,16 @@ __device__ __forceinline__ uint32_t select_blocks(const uint32_t *run, const uin
         } else {
             merge_sorted<L, S>(run, blk, merged);
         }
-        return select_blocks<K, POS + S, NL, T - DLOW>(merged + DLOW, w0, w1);
+        return select_blocks<K, POS + S, NL, T - DLOW>(merged + DLOW, w, win);
     }
 }
 
 template <int K>
-__device__ __forceinline__ uint32_t median_blocks(const uint16_t *w0, const uint16_t *w1) {
-    return select_blocks<K, 0, 0, (K * K - 1) / 2>(nullptr, w0, w1);
-}
-
-template <int K>
-__device__ __forceinline__ uint32_t median_pair(const uint16_t *w0, const uint16_t *w1) {
+__device__ __forceinline__ uint32_t median_pair(const uint16_t *tile, uint32_t o0, uint32_t o1) {
     static_assert(K <= 11, "larger windows select one window per lane in registers");
-    return median_blocks<K>(w0, w1);
+    static_assert(kLdsPitch % 2 == 0, "window rows must keep their parity");
+    uint32_t win[K * K];
+    return select_blocks<K, 0, 0, (K * K - 1) / 2>(nullptr, pair_row(tile, o0, o1), win);
 }
 
 constexpr int kRegisterSelectMin = 13;
@@ -718,7 +776,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
             for (uint32_t i = 2 * slot; i < total; i += 2 * kThreads) {
                 const uint32_t e0 = sm.list[i];
                 const uint32_t e1 = (i + 1 < total) ? sm.list[i + 1] : e0;
-                const uint32_t med = median_pair<K>(sm.tile + e0 - corner, sm.tile + e1 - corner);
+                const uint32_t med = median_pair<K>(sm.tile, e0 - corner, e1 - corner);
                 sm.list[i] = (uint16_t)(med & 0xffffu);
                 if (i + 1 < total) sm.list[i + 1] = (uint16_t)(med >> 16);
             }
@@ -735,11 +793,22 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         }
         // 5. store the thread's block (its own LDS values only: no barrier needed)
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
+        const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            if (py + q >= H) break;
+            if (!full && py + q >= H) break;
             const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * kLdsPitch);
-            store4<T>(dst + (uint64_t)(py + q) * a.dst_pitch, px, W, aligned, c[0], c[1]);
+            uint8_t *row = dst + (uint64_t)(py + q) * a.dst_pitch;
+            if (full) {
+                if constexpr (sizeof(T) == 2) {
+                    *reinterpret_cast<uint2 *>(row + 2 * (uint64_t)px) = make_uint2(c[0], c[1]);
+                } else {
+                    *reinterpret_cast<uint32_t *>(row + px) = (c[0] & 0xffu) | ((c[0] >> 8) & 0xff00u) |
+                                                               ((c[1] & 0xffu) << 16) | ((c[1] & 0xff0000u) << 8);
+                }
+            } else {
+                store4<T>(row, px, W, aligned, c[0], c[1]);
+            }
         }
         return wave_total;
     }

@@ -135,7 +135,7 @@ def test_plan_argument_checks_before_any_device_call(lib):
 
 
 def test_frame_tile_count(lib):
-    assert lib.ir_filter_frame_tiles(640, 512) == 5 * 8
-    assert lib.ir_filter_frame_tiles(129, 65) == 2 * 2
+    assert lib.ir_filter_frame_tiles(640, 512) == 5 * 16
+    assert lib.ir_filter_frame_tiles(129, 65) == 2 * 3
     assert lib.ir_filter_frame_tiles(1, 1) == 1
     assert lib.ir_filter_frame_tiles(0, 5) == 0

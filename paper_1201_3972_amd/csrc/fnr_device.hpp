@@ -39,10 +39,15 @@
 
 namespace irf {
 
-constexpr int kThreads = 128;
+constexpr int kThreads = 128;                // workgroup of the batch kernels
 constexpr int kTileW = 128;                  // output columns per tile
 constexpr int kThreadsX = kTileW / 4;        // 32 threads across, 4 columns each
 constexpr int kStrips = kThreads / kThreadsX;  // 4 strips of R rows
+// Workgroup of the single-size stack kernels, per window: 7x7 takes tiles of
+// twice the height, which fill its selection waves better (a 128x32 tile holds
+// about 80 window pairs to select at the usual impulse rates, just over one
+// wave's worth); the other windows run faster with the smaller tile.
+constexpr int stack_threads(int K) { return K == 7 ? 256 : 128; }
 constexpr int kHalo = 8;                     // LDS columns kept left and right of the tile
 constexpr int kLdsW = kTileW + 2 * kHalo;    // 144 16-bit values staged per LDS row
 constexpr int kChunks = kLdsW / 8;           // 8-pixel load chunks per LDS row
@@ -76,16 +81,17 @@ struct StackArgs {
     uint32_t pk_one;
 };
 
-template <int K>
+template <int K, int NT = kThreads>
 struct Geometry {
     static constexpr int r = K / 2;
     static constexpr int R = 8;  // output rows per thread
-    static constexpr int TH = kStrips * R;
+    static constexpr int TH = NT / kThreadsX * R;
     static constexpr int rows = TH + 2 * r;  // LDS rows
     static constexpr int tile_px = kTileW * TH;
     static constexpr int chunks = rows * kChunks;                      // 8-pixel chunks
-    static constexpr int per_thread = (chunks + kThreads - 1) / kThreads;
+    static constexpr int per_thread = (chunks + NT - 1) / NT;
     static_assert(K >= 3 && K <= kMaxWindow && (K & 1), "odd window 3..15");
+    static_assert(NT % 64 == 0 && NT % kThreadsX == 0, "whole waves of whole thread rows");
     static_assert(r <= kHalo, "halo must cover the window radius");
 };
 
@@ -164,35 +170,24 @@ __device__ __forceinline__ uint4 load_chunk(const uint8_t *rp, int gx, int W, bo
 // frame in LDS (row-major, kLdsPitch values apart), coordinates outside the
 // frame clamped to the nearest edge pixel.  All loads are issued before the
 // first LDS write.
-template <typename T, int K>
+template <typename T, int K, int NT = kThreads>
 __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
                                           int y0, bool aligned, uint16_t *tile) {
-    using G = Geometry<K>;
+    using G = Geometry<K, NT>;
     uint4 v[G::per_thread];
-    // columns of the whole staged tile inside the frame: no per-chunk checks
-    const bool interior = aligned && x0 >= kHalo && x0 + kTileW + kHalo <= W;
 #pragma unroll
     for (int i = 0; i < G::per_thread; ++i) {
-        const int idx = threadIdx.x + i * kThreads;
+        const int idx = threadIdx.x + i * NT;
         if (idx < G::chunks) {
             const int row = idx / kChunks;
             const int c = idx - row * kChunks;
             const int gy = min(max(y0 - G::r + row, 0), H - 1);
-            const uint8_t *rp = src + (uint64_t)gy * pitch;
-            const int gx = x0 - kHalo + 8 * c;
-            if (interior) {
-                if constexpr (sizeof(T) == 2)
-                    v[i] = *reinterpret_cast<const uint4 *>(rp + 2 * (uint64_t)gx);
-                else
-                    v[i] = widen8(*reinterpret_cast<const uint2 *>(rp + gx));
-            } else {
-                v[i] = load_chunk<T>(rp, gx, W, aligned);
-            }
+            v[i] = load_chunk<T>(src + (uint64_t)gy * pitch, x0 - kHalo + 8 * c, W, aligned);
         }
     }
 #pragma unroll
     for (int i = 0; i < G::per_thread; ++i) {
-        const int idx = threadIdx.x + i * kThreads;
+        const int idx = threadIdx.x + i * NT;
         if (idx < G::chunks) {
             const int row = idx / kChunks;
             const int c = idx - row * kChunks;
@@ -672,9 +667,9 @@ __device__ __forceinline__ TileRange xcd_range(int b, int G, int total) {
     return {tb + local, te, nx};
 }
 
-template <int K>
+template <int K, int NT = kThreads>
 struct TileSmem {
-    using G = Geometry<K>;
+    using G = Geometry<K, NT>;
     uint16_t tile[G::rows * kLdsPitch];
     uint16_t list[G::tile_px];  // LDS offsets of flagged centres, then their medians
     uint32_t count;             // list length
@@ -683,9 +678,9 @@ struct TileSmem {
 // One tile already staged in LDS: detection, compaction of the flagged pixels,
 // selection, then the tile (flagged pixels replaced) is stored.  Returns the
 // number of flagged pixels the calling wave found (wave-uniform).
-template <typename T, int K, int MODE>
-__device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K> &sm) {
-    using G = Geometry<K>;
+template <typename T, int K, int MODE, int NT = kThreads>
+__device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K, NT> &sm) {
+    using G = Geometry<K, NT>;
     constexpr int R = G::R;
     const int f = tile / a.tiles_per_frame;
     const int rem = tile - f * a.tiles_per_frame;
@@ -766,14 +761,14 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         constexpr int corner = G::r * kLdsPitch + G::r;
         if constexpr (K >= kRegisterSelectMin) {
             // one window per lane
-            const uint32_t slot = (uint32_t)(tid + 64 * (tile & 3)) % kThreads;
-            for (uint32_t i = slot; i < total; i += kThreads) {
+            const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)tile) % NT;
+            for (uint32_t i = slot; i < total; i += NT) {
                 const uint32_t e0 = sm.list[i];
                 sm.list[i] = (uint16_t)median_registers<K>(sm.tile + e0 - corner);
             }
         } else {
-            const uint32_t slot = (uint32_t)(tid + 64 * (tile & 3)) % kThreads;
-            for (uint32_t i = 2 * slot; i < total; i += 2 * kThreads) {
+            const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)tile) % NT;
+            for (uint32_t i = 2 * slot; i < total; i += 2 * NT) {
                 const uint32_t e0 = sm.list[i];
                 const uint32_t e1 = (i + 1 < total) ? sm.list[i + 1] : e0;
                 const uint32_t med = median_pair<K>(sm.tile, e0 - corner, e1 - corner);
@@ -828,9 +823,10 @@ __device__ __forceinline__ void tile_origin(const StackArgs &a, int tile, int th
 // after the flagged list is complete and after the selection.  Other resident
 // workgroups run while one waits for its tile's loads.
 template <typename T, int K, int MODE>
-__global__ __launch_bounds__(kThreads) void fnr_persistent_kernel(StackArgs a) {
-    using G = Geometry<K>;
-    __shared__ __attribute__((aligned(16))) TileSmem<K> sm;
+__global__ __launch_bounds__(stack_threads(K)) void fnr_persistent_kernel(StackArgs a) {
+    constexpr int NT = stack_threads(K);
+    using G = Geometry<K, NT>;
+    __shared__ __attribute__((aligned(16))) TileSmem<K, NT> sm;
     const TileRange rg = xcd_range(blockIdx.x, gridDim.x, a.total_tiles);
     const bool aligned = a.aligned != 0;
     uint32_t flagged = 0;  // this wave's noisy pixels over all its tiles
@@ -838,11 +834,11 @@ __global__ __launch_bounds__(kThreads) void fnr_persistent_kernel(StackArgs a) {
         int f, x0, y0;
         tile_origin(a, t, G::TH, f, x0, y0);
         __syncthreads();  // the previous tile is no longer read
-        load_tile<T, K>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, a.width, a.height, x0, y0,
+        load_tile<T, K, NT>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, a.width, a.height, x0, y0,
                         aligned, sm.tile);
         if (threadIdx.x == 0) sm.count = 0;
         __syncthreads();
-        flagged += process_tile<T, K, MODE>(a, t, sm);
+        flagged += process_tile<T, K, MODE, NT>(a, t, sm);
     }
     if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR) {
         if (a.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)

@@ -18,10 +18,7 @@ using namespace host;
 
 constexpr int kVersion = (1 << 16) | 0;
 
-int tile_rows(int window) {
-    (void)window;
-    return kStrips * Geometry<3>::R;  // every window uses the same tile height
-}
+int tile_rows(int window) { return stack_threads(window) / kThreadsX * Geometry<3>::R; }
 
 // Persistent grid: as many workgroups as fit on the device at once (never more
 // than there are tiles).
@@ -29,7 +26,7 @@ template <typename T, int K, int MODE>
 int persistent_grid(int total_tiles) {
     static const int per_cu = [] {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_persistent_kernel<T, K, MODE>, kThreads,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_persistent_kernel<T, K, MODE>, stack_threads(K),
                                                          0) != hipSuccess ||
             n < 1)
             n = 1;
@@ -42,7 +39,7 @@ int persistent_grid(int total_tiles) {
 template <typename T, int K, int MODE>
 void launch_t(const StackArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((fnr_persistent_kernel<T, K, MODE>), dim3(persistent_grid<T, K, MODE>(a.total_tiles)),
-                       dim3(kThreads), 0, s, a);
+                       dim3(stack_threads(K)), 0, s, a);
 }
 
 template <typename T, int MODE>

@@ -17,8 +17,11 @@
  * window; 16-bit pixels are compared as full 16-bit values.
  *
  * Frames are single-channel, row-major, uint8 or uint16.  A "pitch" is the
- * byte distance between the starts of two rows (>= width * bytes per pixel);
- * only the first width * bytes bytes of each row are read or written.
+ * byte distance between the starts of two rows (>= width * bytes per pixel,
+ * < 2^24); a frame's span, (height - 1) * pitch + width * bytes per pixel, is
+ * below 4 GiB (rows are addressed with 32-bit offsets inside a frame; frames
+ * of a stack may lie anywhere).  Only the first width * bytes bytes of each
+ * row are read or written.
  *
  * Memory and ownership: every frame, mask, scratch and counter pointer is a
  * DEVICE pointer owned by the caller (e.g. a torch CUDA tensor's data_ptr()).
@@ -54,7 +57,8 @@ typedef enum {
     IRF_OK = 0,
     IRF_ERR_NULL = -1,    /* a required pointer is NULL */
     IRF_ERR_DIMS = -2,    /* width/height outside 1..IRF_MAX_DIM, or frame count < 1 */
-    IRF_ERR_PITCH = -3,   /* a pitch is smaller than one row, or a stride smaller than one frame */
+    IRF_ERR_PITCH = -3,   /* a pitch is smaller than one row or not below 2^24, a frame spans
+                             4 GiB or more, or a stride is smaller than one frame */
     IRF_ERR_DTYPE = -4,   /* pixel type is not IRF_U8 or IRF_U16 */
     IRF_ERR_WINDOW = -5,  /* window is not odd or outside 3..IRF_MAX_WINDOW */
     IRF_ERR_PASSES = -6,  /* passes outside 1..IRF_MAX_PASSES, or scratch missing for passes >= 2 */

@@ -69,7 +69,7 @@ struct StackArgs {
     uint8_t *dst;            // MODE_FNR / MODE_MEDIAN_*
     const uint8_t *mask_in;  // MODE_MEDIAN_MASK
     uint8_t *mask_out;       // MODE_DETECT
-    uint64_t src_pitch, dst_pitch, mask_pitch;     // bytes between rows
+    uint64_t src_pitch, dst_pitch, mask_pitch;     // bytes between rows (< 2^24)
     uint64_t src_stride, dst_stride, mask_stride;  // bytes between frames
     int width, height;
     int tiles_x, tiles_per_frame;
@@ -88,8 +88,6 @@ struct Geometry {
     static constexpr int TH = NT / kThreadsX * R;
     static constexpr int rows = TH + 2 * r;  // LDS rows
     static constexpr int tile_px = kTileW * TH;
-    static constexpr int chunks = rows * kChunks;                      // 8-pixel chunks
-    static constexpr int per_thread = (chunks + NT - 1) / NT;
     static_assert(K >= 3 && K <= kMaxWindow && (K & 1), "odd window 3..15");
     static_assert(NT % 64 == 0 && NT % kThreadsX == 0, "whole waves of whole thread rows");
     static_assert(r <= kHalo, "halo must cover the window radius");
@@ -124,12 +122,15 @@ __device__ __forceinline__ uint32_t shift_pair(uint32_t hi_word, uint32_t lo_wor
 // ---------------------------------------------------------------------------
 // 1. tile load
 // ---------------------------------------------------------------------------
+// Addresses inside a frame are 32-bit byte offsets from the frame's base (the
+// host keeps every frame's span below 4 GiB and its pitch below 2^24 bytes), so
+// the base stays in scalar registers and a row offset is one 24-bit multiply.
 template <typename T>
-__device__ __forceinline__ uint32_t load_px(const uint8_t *row, int x) {
+__device__ __forceinline__ uint32_t load_px(const uint8_t *frame, uint32_t row_off, int x) {
     if constexpr (sizeof(T) == 1)
-        return row[x];
+        return frame[row_off + (uint32_t)x];
     else
-        return reinterpret_cast<const uint16_t *>(row)[x];
+        return *reinterpret_cast<const uint16_t *>(frame + (row_off + 2u * (uint32_t)x));
 }
 
 __device__ __forceinline__ uint4 widen8(uint2 b) {
@@ -146,54 +147,67 @@ __device__ __forceinline__ uint4 splat8(uint32_t v) {
     return make_uint4(p, p, p, p);
 }
 
-// One 8-pixel chunk of frame row gy starting at column gx, columns clamped to
-// the frame: a vector load when the chunk lies inside (and the layout is
-// 16-byte aligned), one pixel repeated when it lies wholly left or right of the
-// frame, per-pixel clamped loads when it straddles an edge.
+// One 8-pixel chunk of the frame row at byte offset row_off, starting at column
+// gx, columns clamped to the frame: a vector load when the chunk lies inside
+// (and the layout is 16-byte aligned), one pixel repeated when it lies wholly
+// left or right of the frame, per-pixel clamped loads when it straddles an edge.
 template <typename T>
-__device__ __forceinline__ uint4 load_chunk(const uint8_t *rp, int gx, int W, bool aligned) {
+__device__ __forceinline__ uint4 load_chunk(const uint8_t *frame, uint32_t row_off, int gx, int W,
+                                            bool aligned) {
     if (aligned && gx >= 0 && gx + 8 <= W) {
+        const uint32_t off = row_off + (uint32_t)gx * (uint32_t)sizeof(T);
         if constexpr (sizeof(T) == 2)
-            return *reinterpret_cast<const uint4 *>(rp + 2 * (uint64_t)gx);
+            return *reinterpret_cast<const uint4 *>(frame + off);
         else
-            return widen8(*reinterpret_cast<const uint2 *>(rp + gx));
+            return widen8(*reinterpret_cast<const uint2 *>(frame + off));
     }
-    if (gx + 8 <= 0) return splat8(load_px<T>(rp, 0));
-    if (gx >= W) return splat8(load_px<T>(rp, W - 1));
+    if (gx + 8 <= 0) return splat8(load_px<T>(frame, row_off, 0));
+    if (gx >= W) return splat8(load_px<T>(frame, row_off, W - 1));
     uint32_t e[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) e[i] = load_px<T>(rp, min(max(gx + i, 0), W - 1));
+    for (int i = 0; i < 8; ++i) e[i] = load_px<T>(frame, row_off, min(max(gx + i, 0), W - 1));
     return make_uint4(e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16));
 }
 
 // Stage rows y0-r .. y0+TH+r-1 and columns x0-kHalo .. x0+kTileW+kHalo-1 of a
 // frame in LDS (row-major, kLdsPitch values apart), coordinates outside the
-// frame clamped to the nearest edge pixel.  All loads are issued before the
-// first LDS write.
+// frame clamped to the nearest edge pixel.  Each row is 16 interior chunks and
+// two halo chunks: thread t loads interior chunk t % 16 of rows t / 16,
+// t / 16 + NT / 16, ... and, if t < 2 * rows, the left (t even) or right halo
+// chunk of row t / 2, so a thread's column is the same on every tile.  All
+// loads are issued before the first LDS write.
 template <typename T, int K, int NT = kThreads>
 __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
                                           int y0, bool aligned, uint16_t *tile) {
     using G = Geometry<K, NT>;
-    uint4 v[G::per_thread];
+    constexpr int kStep = NT / 16;
+    constexpr int kRounds = (G::rows + kStep - 1) / kStep;
+    static_assert(kTileW == 16 * 8 && kChunks == 18, "16 interior and 2 halo chunks per row");
+    static_assert(2 * G::rows <= NT, "at most one halo chunk per thread");
+    const int tid = threadIdx.x;
+    const int cx = tid & 15, row0 = tid >> 4;
+    const int hrow = tid >> 1, hcol = (tid & 1) ? kChunks - 1 : 0;
+    const int ytop = y0 - G::r;
+    uint4 v[kRounds], h;
 #pragma unroll
-    for (int i = 0; i < G::per_thread; ++i) {
-        const int idx = threadIdx.x + i * NT;
-        if (idx < G::chunks) {
-            const int row = idx / kChunks;
-            const int c = idx - row * kChunks;
-            const int gy = min(max(y0 - G::r + row, 0), H - 1);
-            v[i] = load_chunk<T>(src + (uint64_t)gy * pitch, x0 - kHalo + 8 * c, W, aligned);
+    for (int j = 0; j < kRounds; ++j) {
+        const int row = row0 + j * kStep;
+        if (j < kRounds - 1 || row < G::rows) {
+            const int gy = min(max(ytop + row, 0), H - 1);
+            v[j] = load_chunk<T>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 + 8 * cx, W, aligned);
         }
     }
-#pragma unroll
-    for (int i = 0; i < G::per_thread; ++i) {
-        const int idx = threadIdx.x + i * NT;
-        if (idx < G::chunks) {
-            const int row = idx / kChunks;
-            const int c = idx - row * kChunks;
-            *reinterpret_cast<uint4 *>(tile + row * kLdsPitch + 8 * c) = v[i];
-        }
+    if (tid < 2 * G::rows) {
+        const int gy = min(max(ytop + hrow, 0), H - 1);
+        h = load_chunk<T>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 - kHalo + 8 * hcol, W, aligned);
     }
+#pragma unroll
+    for (int j = 0; j < kRounds; ++j) {
+        const int row = row0 + j * kStep;
+        if (j < kRounds - 1 || row < G::rows)
+            *reinterpret_cast<uint4 *>(tile + row * kLdsPitch + 8 * (cx + 1)) = v[j];
+    }
+    if (tid < 2 * G::rows) *reinterpret_cast<uint4 *>(tile + hrow * kLdsPitch + 8 * hcol) = h;
 }
 
 // ---------------------------------------------------------------------------
@@ -618,30 +632,32 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
 // 5. stores
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void store_px(uint8_t *row, int x, uint32_t v) {
+__device__ __forceinline__ void store_px(uint8_t *frame, uint32_t row_off, int x, uint32_t v) {
     if constexpr (sizeof(T) == 1)
-        row[x] = (uint8_t)v;
+        frame[row_off + (uint32_t)x] = (uint8_t)v;
     else
-        reinterpret_cast<uint16_t *>(row)[x] = (uint16_t)v;
+        *reinterpret_cast<uint16_t *>(frame + (row_off + 2u * (uint32_t)x)) = (uint16_t)v;
 }
 
-// Four 16-bit LDS values (two packed pairs) to the frame row at column px.
+// Four 16-bit LDS values (two packed pairs) to the frame row at byte offset
+// row_off, column px.
 template <typename T>
-__device__ __forceinline__ void store4(uint8_t *row, int px, int W, bool aligned, uint32_t p0,
-                                       uint32_t p1) {
+__device__ __forceinline__ void store4(uint8_t *frame, uint32_t row_off, int px, int W, bool aligned,
+                                       uint32_t p0, uint32_t p1) {
     if (aligned && px + 4 <= W) {
+        const uint32_t off = row_off + (uint32_t)px * (uint32_t)sizeof(T);
         if constexpr (sizeof(T) == 2) {
-            *reinterpret_cast<uint2 *>(row + 2 * (uint64_t)px) = make_uint2(p0, p1);
+            *reinterpret_cast<uint2 *>(frame + off) = make_uint2(p0, p1);
         } else {
             uint32_t b = (p0 & 0xffu) | ((p0 >> 8) & 0xff00u) | ((p1 & 0xffu) << 16) |
                          ((p1 & 0xff0000u) << 8);
-            *reinterpret_cast<uint32_t *>(row + px) = b;
+            *reinterpret_cast<uint32_t *>(frame + off) = b;
         }
     } else {
         uint32_t e[4] = {p0 & 0xffffu, p0 >> 16, p1 & 0xffffu, p1 >> 16};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (px + i < W) store_px<T>(row, px + i, e[i]);
+            if (px + i < W) store_px<T>(frame, row_off, px + i, e[i]);
     }
 }
 
@@ -703,10 +719,10 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if (py + q >= H) break;
-            const uint8_t *mr = m + (uint64_t)(py + q) * a.mask_pitch;
+            const uint32_t mo = __umul24((uint32_t)(py + q), (uint32_t)a.mask_pitch) + (uint32_t)px;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                if (px + e < W && mr[px + e] != 0) {
+                if (px + e < W && m[mo + (uint32_t)e] != 0) {
                     const int sh = (e == 0) ? 0 : (e == 1) ? 16 : (e == 2) ? 8 : 24;
                     flags |= 1u << (q + sh);
                 }
@@ -726,15 +742,15 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if (py + q >= H) break;
-            uint8_t *mr = m + (uint64_t)(py + q) * a.mask_pitch;
+            const uint32_t mo = __umul24((uint32_t)(py + q), (uint32_t)a.mask_pitch) + (uint32_t)px;
             const uint32_t b0 = (flags >> q) & 1u, b1 = (flags >> (q + 16)) & 1u;
             const uint32_t b2 = (flags >> (q + 8)) & 1u, b3 = (flags >> (q + 24)) & 1u;
             if (aligned && px + 4 <= W) {
-                *reinterpret_cast<uint32_t *>(mr + px) = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+                *reinterpret_cast<uint32_t *>(m + mo) = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
             } else {
                 const uint32_t e[4] = {b0, b1, b2, b3};
                 for (int i = 0; i < 4; ++i)
-                    if (px + i < W) mr[px + i] = (uint8_t)e[i];
+                    if (px + i < W) m[mo + (uint32_t)i] = (uint8_t)e[i];
             }
         }
         return wave_total;
@@ -793,16 +809,17 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         for (int q = 0; q < R; ++q) {
             if (!full && py + q >= H) break;
             const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * kLdsPitch);
-            uint8_t *row = dst + (uint64_t)(py + q) * a.dst_pitch;
+            const uint32_t ro = __umul24((uint32_t)(py + q), (uint32_t)a.dst_pitch);
             if (full) {
+                const uint32_t off = ro + (uint32_t)px * (uint32_t)sizeof(T);
                 if constexpr (sizeof(T) == 2) {
-                    *reinterpret_cast<uint2 *>(row + 2 * (uint64_t)px) = make_uint2(c[0], c[1]);
+                    *reinterpret_cast<uint2 *>(dst + off) = make_uint2(c[0], c[1]);
                 } else {
-                    *reinterpret_cast<uint32_t *>(row + px) = (c[0] & 0xffu) | ((c[0] >> 8) & 0xff00u) |
+                    *reinterpret_cast<uint32_t *>(dst + off) = (c[0] & 0xffu) | ((c[0] >> 8) & 0xff00u) |
                                                                ((c[1] & 0xffu) << 16) | ((c[1] & 0xff0000u) << 8);
                 }
             } else {
-                store4<T>(row, px, W, aligned, c[0], c[1]);
+                store4<T>(dst, ro, px, W, aligned, c[0], c[1]);
             }
         }
         return wave_total;

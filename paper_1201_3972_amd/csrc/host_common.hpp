@@ -38,8 +38,17 @@ inline irf_status check_common(int width, int height, int nframes, irf_dtype dty
     return IRF_OK;
 }
 
+// Device code addresses a frame with 32-bit byte offsets from its base and
+// 24-bit row multiplies: a pitch must stay below 2^24 bytes and a frame's span
+// below 4 GiB.
+constexpr size_t kMaxPitch = ((size_t)1 << 24) - 1;
+constexpr uint64_t kMaxFrameSpan = ((uint64_t)1 << 32) - 1;
+
 inline irf_status check_layout(size_t pitch, size_t stride, int width, int height, int nframes, int bytes) {
     if (pitch < (size_t)width * (size_t)bytes) return IRF_ERR_PITCH;
+    if (pitch > kMaxPitch) return IRF_ERR_PITCH;
+    if ((uint64_t)pitch * (uint64_t)(height - 1) + (uint64_t)width * (uint64_t)bytes > kMaxFrameSpan)
+        return IRF_ERR_PITCH;
     if (nframes > 1 && stride < pitch * (size_t)height) return IRF_ERR_PITCH;
     return IRF_OK;
 }

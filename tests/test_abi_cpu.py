@@ -84,6 +84,18 @@ def test_run_validation(lib, kw, want):
     assert run(lib, **kw) == want
 
 
+def test_pitch_and_span_limits(lib):
+    # rows are addressed with 24-bit multiplies and 32-bit offsets inside a frame
+    assert run(lib, sp=1 << 24) == -3
+    assert run(lib, dp=1 << 24) == -3
+    big = (1 << 24) - 16
+    assert big * 299 + 320 >= 1 << 32
+    assert run(lib, sp=big, H=300) == -3
+    assert run(lib, dp=big, H=300) == -3
+    f = lib.ir_filter_detect
+    assert f(SRC, 640, MASK, 1 << 24, 320, 240, 1, 3, None, None) == -3
+
+
 def test_last_byte_of_source_counts_for_aliasing(lib):
     end = SRC + 640 * 239 + 320  # one past the last byte read from src
     assert run(lib, dst=end - 1) == -7

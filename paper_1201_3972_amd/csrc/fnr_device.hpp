@@ -618,14 +618,20 @@ __device__ __forceinline__ uint32_t median_registers(const uint16_t *w) {
 // ---------------------------------------------------------------------------
 // wave / workgroup prefix sums
 // ---------------------------------------------------------------------------
+// Inclusive prefix sum over the wave with DPP moves: a Hillis-Steele scan
+// inside each row of 16 lanes (row_shr 1, 2, 4, 8; lanes shifted in from
+// outside the row read 0), then row 15's total is added to rows 1 and 3
+// (row_bcast:15) and row 31's to rows 2 and 3 (row_bcast:31).
 __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
-    return v;
+    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 2, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 4, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 8, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowBcast15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowBcast31, 0xc, 0xf, false);
+    return (uint32_t)x;
 }
 
 // ---------------------------------------------------------------------------
@@ -775,15 +781,14 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         //    that as few waves as possible run the selection; which wave starts
         //    the list rotates with the tile (waves sit on fixed SIMDs)
         constexpr int corner = G::r * kLdsPitch + G::r;
+        const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)tile) % NT;
         if constexpr (K >= kRegisterSelectMin) {
             // one window per lane
-            const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)tile) % NT;
             for (uint32_t i = slot; i < total; i += NT) {
                 const uint32_t e0 = sm.list[i];
                 sm.list[i] = (uint16_t)median_registers<K>(sm.tile + e0 - corner);
             }
         } else {
-            const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)tile) % NT;
             for (uint32_t i = 2 * slot; i < total; i += 2 * NT) {
                 const uint32_t e0 = sm.list[i];
                 const uint32_t e1 = (i + 1 < total) ? sm.list[i + 1] : e0;

@@ -205,8 +205,15 @@ def section_c4(torch, irfilter, synth, oracle, dev) -> dict:
             irfilter.ir_filter_run(a, r, it.window)
 
     ms_pf = _timed(torch, per_frame, 5)
-    ms_b = _timed(torch, lambda: plan.run_frames(arr, len(items)), 10)
-    ms_g = _timed(torch, lambda: plan_g.run_frames(arr, len(items)), 10)
+    # direct and graph-replayed launches alternate over four rounds; each form
+    # reports its best round (graph replays have run slower for a while after
+    # other allocations, then at the direct launch's speed), and the graph's
+    # first round is kept as well
+    rounds_b, rounds_g = [], []
+    for _ in range(4):
+        rounds_b.append(_timed(torch, lambda: plan.run_frames(arr, len(items)), 10))
+        rounds_g.append(_timed(torch, lambda: plan_g.run_frames(arr, len(items)), 10))
+    ms_b, ms_g = min(rounds_b), min(rounds_g)
     plan.close()
     plan_g.close()
     b = sum(fr.size * fr.itemsize for fr in frames) * 2
@@ -215,7 +222,8 @@ def section_c4(torch, irfilter, synth, oracle, dev) -> dict:
             "per_frame": {"ms": round(ms_pf, 3), "MP_per_s": round(px / ms_pf / 1e3, 1)},
             "batched": {"ms": round(ms_b, 3), "MP_per_s": round(px / ms_b / 1e3, 1),
                         "algorithmic_GBps": round(b / ms_b / 1e6, 1)},
-            "batched_graph": {"ms": round(ms_g, 3), "MP_per_s": round(px / ms_g / 1e3, 1)},
+            "batched_graph": {"ms": round(ms_g, 3), "MP_per_s": round(px / ms_g / 1e3, 1),
+                              "first_round_ms": round(rounds_g[0], 3)},
             "batched_over_per_frame": round(ms_pf / min(ms_b, ms_g), 2)}
 
 

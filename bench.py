@@ -94,9 +94,12 @@ def ingest_counters(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out_path=TRAFF
         "bytes": 1 << 30, "fetch_kib": fk, "write_kib": wk, "fetch_scale": ff, "write_scale": wf},
         "windows": {}}
     for name, vs in fetch.items():
-        if "fnr_persistent_kernel<unsigned short," not in name or ", 1>" not in name:
+        if "fnr_persistent_kernel<unsigned short," not in name:
             continue
-        k = int(name.split("unsigned short,")[1].split(",")[0])
+        targs = [x.strip() for x in name.split("fnr_persistent_kernel<", 1)[1].split(">", 1)[0].split(",")]
+        if len(targs) < 3 or targs[2] != "1":  # MODE_FNR only
+            continue
+        k = int(targs[1])
         f_kib = sum(vs) / len(vs)
         w_kib = sum(write[name]) / len(write[name])
         rec["windows"][str(k)] = {"kernel": name, "fetch_kib": f_kib, "write_kib": w_kib,
@@ -147,9 +150,13 @@ def section_c1(torch, irfilter, synth, oracle, dev) -> dict:
             "host_latency_p99_ms": round(float(np.percentile(lat, 99)), 4)}
 
 
-def section_c3(torch, irfilter, synth, oracle, dev, frames: int = 64) -> dict:
-    """1920x1080 u16, 40 % mixed impulses, windows 3..15: a stack per window."""
+def section_c3(torch, irfilter, synth, oracle, dev, frames: int = 64, tune: bool = True) -> dict:
+    """1920x1080 u16, 40 % mixed impulses, windows 3..15: a stack per window
+    (workgroup size and selection algorithm autotuned on this frame first)."""
     f = synth.make_frame(synth.c3_spec())
+    if tune:
+        from paper_1201_3972_amd import autotune
+        autotune.tune_single(torch, "u16", windows=synth.C3_WINDOWS, frames=16, rounds=2, pool=[f])
     src = torch.empty((frames, 1080, 1920), dtype=torch.uint16, device=dev)
     one = to_dev(torch, f, dev)
     for i in range(frames):
@@ -166,15 +173,21 @@ def section_c3(torch, irfilter, synth, oracle, dev, frames: int = 64) -> dict:
             raise RuntimeError(f"c3 parity failure at window {k}")
         ms = _timed(torch, lambda: irfilter.ir_filter_run_frames(src, dst, k), 5)
         px = frames * 1920 * 1080
+        th, sel = irfilter.get_tuning("u16", k)
         out["windows"][str(k)] = {"ms": round(ms, 3), "MP_per_s": round(px / ms / 1e3, 1),
-                                  "algorithmic_GBps": round(4 * px / ms / 1e6, 1)}
+                                  "algorithmic_GBps": round(4 * px / ms / 1e6, 1),
+                                  "threads": th, "select": irfilter.SELECT_NAMES[sel]}
     return out
 
 
-def section_c4(torch, irfilter, synth, oracle, dev) -> dict:
+def section_c4(torch, irfilter, synth, oracle, dev, tune: bool = True) -> dict:
     """256 uneven frames (160x120..1280x1024, u8/u16, windows 3/5/7/9): plain
     per-frame launches against one persistent batched launch (with and
-    without graph replay)."""
+    without graph replay), under the autotuned batch workgroup size."""
+    tuned = None
+    if tune:
+        from paper_1201_3972_amd import autotune
+        tuned = autotune.tune_batch(torch, n=256)
     items = synth.c4_items(256)
     frames = [synth.make_frame(it.spec) for it in items]
     srcs = [to_dev(torch, fr, dev) if fr.dtype == np.uint16 else torch.from_numpy(fr).to(dev) for fr in frames]
@@ -219,6 +232,7 @@ def section_c4(torch, irfilter, synth, oracle, dev) -> dict:
     b = sum(fr.size * fr.itemsize for fr in frames) * 2
     return {"workload": "256 frames W~U{160..1280} x H~U{120..1024}, u8/u16, windows 3/5/7/9, "
                         "5-60% mixed impulses", "pixels": px, "tiles": tiles,
+            "batch_threads": irfilter.get_batch_threads(), "batch_tuning_ms": None if tuned is None else tuned["ms"],
             "per_frame": {"ms": round(ms_pf, 3), "MP_per_s": round(px / ms_pf / 1e3, 1)},
             "batched": {"ms": round(ms_b, 3), "MP_per_s": round(px / ms_b / 1e3, 1),
                         "algorithmic_GBps": round(b / ms_b / 1e6, 1)},
@@ -265,6 +279,8 @@ def main() -> int:
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--sections", default="c1,c3,c4,c5",
                     help="extra workloads reported beside the headline (comma list, or 'none')")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner and run the library's untuned choices")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the HBM traffic record from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
@@ -313,6 +329,16 @@ def main() -> int:
     counts = {k: torch.zeros(1, dtype=torch.int64, device=dev) for k in windows}
     torch.cuda.synchronize()
     log(f"inputs: {N} frames of {W}x{H} u16 from {P} distinct ({time.time() - t0:.1f}s)")
+
+    # ---- autotune (workgroup size and selection algorithm per window) on this workload ----
+    tuning = None
+    if not args.no_tune:
+        from paper_1201_3972_amd import autotune
+        t0 = time.time()
+        tuning = autotune.tune_single(torch, "u16", windows=windows, frames=min(N, 256), rounds=3,
+                                      pool=pool, log=log)
+        log(f"autotuned in {time.time() - t0:.1f}s")
+    chosen = {k: irfilter.get_tuning("u16", k) for k in windows}
 
     # ---- parity gate: every output frame vs the oracle, before any timing ----
     import oracle  # test infrastructure: the check, not the product path
@@ -377,7 +403,8 @@ def main() -> int:
     traffic = load_traffic(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"fnr_persistent_kernel<u16,{dom},FNR>",
+                "kernel": f"fnr_persistent_kernel<u16,{dom},FNR,{chosen[dom][0]},"
+                          f"{irfilter.SELECT_NAMES[chosen[dom][1]]}>",
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "per_window_GBps": {str(k): round(bytes_per_launch / (kern_ms[k] * 1e-3) / 1e9, 1)
                                     for k in windows}}
@@ -443,9 +470,9 @@ def main() -> int:
         if name == "c1":
             sections["c1_single_frame"] = section_c1(torch, irfilter, synth, oracle, dev)
         elif name == "c3":
-            sections["c3_window_sweep"] = section_c3(torch, irfilter, synth, oracle, dev)
+            sections["c3_window_sweep"] = section_c3(torch, irfilter, synth, oracle, dev, tune=not args.no_tune)
         elif name == "c4":
-            sections["c4_uneven_batch"] = section_c4(torch, irfilter, synth, oracle, dev)
+            sections["c4_uneven_batch"] = section_c4(torch, irfilter, synth, oracle, dev, tune=not args.no_tune)
         elif name == "c5":
             from paper_1201_3972_amd import serving
             sections["c5_serving"] = section_c5(torch, serving, dev)
@@ -461,6 +488,9 @@ def main() -> int:
                    "passes": 1, "flagged_fraction": {str(k): round(v, 4) for k, v in flag_rate.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "tuning": {str(k): {"threads": chosen[k][0], "select": irfilter.SELECT_NAMES[chosen[k][1]],
+                            "candidates_ms": None if tuning is None else tuning[str(k)]["ms"]}
+                   for k in windows},
         "per_frame": per_frame,
         "latency": latency,
         **sections,

@@ -65,7 +65,8 @@ typedef enum {
     IRF_ERR_ALIAS = -7,   /* an output overlaps an input or another output */
     IRF_ERR_HIP = -8,     /* a HIP call failed (the HIP error is cleared) */
     IRF_ERR_NOMEM = -9,   /* device or host allocation failed (plans only) */
-    IRF_ERR_CAPACITY = -10 /* a batch exceeds the plan's capacity */
+    IRF_ERR_CAPACITY = -10, /* a batch exceeds the plan's capacity */
+    IRF_ERR_TUNING = -11    /* no kernel for that workgroup size and selection algorithm */
 } irf_status;
 
 #define IRF_MAX_DIM 32768
@@ -150,7 +151,9 @@ typedef struct irf_plan irf_plan;
 /*
  * ir_filter_plan_create -- allocate a plan for batches of at most max_frames
  * frames holding at most max_tiles tiles in total (a frame of W x H has
- * ceil(W/128) * ceil(H/64) tiles).  The plan owns two sets of device tables
+ * ceil(W/128) * ceil(H/TH) tiles, TH = 32 or 64 rows for batch workgroups of
+ * 128 or 256 threads: the batch tuning in force when the plan is created, see
+ * ir_filter_set_batch_threads).  The plan owns two sets of device tables
  * (frame descriptors, tile map, work queues) with pinned host staging, used
  * alternately by consecutive batches; it is not thread-safe.  Returns
  * IRF_ERR_NOMEM or IRF_ERR_HIP on failure (*plan is then NULL).
@@ -173,8 +176,38 @@ irf_status ir_filter_run_batch(irf_plan *plan, const irf_frame *frames, int n,
 /* Release a plan (waits for its outstanding work).  NULL is ignored. */
 void ir_filter_plan_destroy(irf_plan *plan);
 
-/* Tiles of one frame as counted against a plan's max_tiles. */
+/* Tiles of one frame as counted against the max_tiles of a plan created under
+ * the current batch tuning. */
 int ir_filter_frame_tiles(int width, int height);
+
+/*
+ * Tuning.  Not part of the method: these choices change the speed of a call,
+ * never its result (every combination computes the same order statistic and
+ * is tested bit-exact against the same oracle).  The table is process-wide;
+ * set it before launching (a launch reads its entry once, but a change while
+ * other host threads launch has no defined order with their launches).
+ *
+ * Single-size entry points (ir_filter_detect / _median / _run / _run_frames):
+ * per pixel type and window, the workgroup size (128 threads on tiles of
+ * 128x32 pixels, or 256 threads on 128x64) and the selection algorithm:
+ *   IRF_SELECT_NETWORK  forgetful selection networks, two windows per lane
+ *                       (windows up to 11x11)
+ *   IRF_SELECT_BISECT   grey-level bisection, one window per lane (any window)
+ * Untuned defaults: 128 threads except 256 for 7x7; networks up to 11x11,
+ * bisection for 13x13 and 15x15.  ir_filter_set_tuning(dtype, window, 0, 0)
+ * restores the default; an unavailable combination returns IRF_ERR_TUNING.
+ * The autotuner of the Python package measures the choices and sets them.
+ */
+typedef enum { IRF_SELECT_NETWORK = 1, IRF_SELECT_BISECT = 2 } irf_select;
+
+irf_status ir_filter_get_tuning(irf_dtype dtype, int window, int *threads, int *select);
+irf_status ir_filter_set_tuning(irf_dtype dtype, int window, int threads, int select);
+
+/* Batch workgroup size for plans created from now on: 128 (tiles of 128x32,
+ * the default) or 256 (128x64); 0 restores the default.  Other values return
+ * IRF_ERR_TUNING. */
+irf_status ir_filter_set_batch_threads(int threads);
+int ir_filter_get_batch_threads(void);
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char *ir_filter_status_string(irf_status status);

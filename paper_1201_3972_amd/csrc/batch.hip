@@ -2,6 +2,8 @@
 // type and window (see include/irfilter.h and batch_device.hpp).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <stdint.h>
 #include <string.h>
 
@@ -22,16 +24,24 @@ constexpr int kSets = 2;          // device table sets used alternately
 constexpr size_t kQueueBytes = 64;  // one BatchQueue record per class, padded
 static_assert(kBatchClasses * sizeof(BatchQueue) <= kQueueBytes, "queue records overflow");
 
-int frame_tiles(int width, int height) {
-    const int th = kStrips * Geometry<3>::R;
+// Workgroup size of plans created from now on (0 = the default, 128 threads).
+std::atomic<int> g_batch_threads{0};
+
+int batch_threads_now() {
+    const int t = g_batch_threads.load(std::memory_order_relaxed);
+    return t == 0 ? kThreads : t;
+}
+
+int frame_tiles(int width, int height, int threads) {
+    const int th = threads / kThreadsX * Geometry<3>::R;
     return ((width + kTileW - 1) / kTileW) * ((height + th - 1) / th);
 }
 
-template <int CLASS>
+template <int CLASS, int NT>
 int batch_grid() {
     static const int per_cu = [] {
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_batch_kernel<CLASS>, kThreads, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_batch_kernel<CLASS, NT>, NT, 0) !=
                 hipSuccess ||
             n < 1)
             n = 1;
@@ -47,6 +57,7 @@ struct irf_plan {
     int max_frames = 0, max_tiles = 0;
     unsigned flags = 0;
     size_t desc_off = 0, map_off = 0, bytes = 0;
+    int threads = kThreads;  // workgroup size of the batch kernels (tile height / 8 * 32)
     int grid[kBatchClasses] = {};
     int next_set = 0;
     struct Set {
@@ -69,9 +80,13 @@ template <int CLASS>
 void launch_class(const irf_plan *p, const irf_plan::Set &s, hipStream_t stream) {
     BatchQueue *q = reinterpret_cast<BatchQueue *>(s.dev);
     const FrameDesc *d = reinterpret_cast<const FrameDesc *>(s.dev + p->desc_off);
-    const uint32_t *map = reinterpret_cast<const uint32_t *>(s.dev + p->map_off);
-    hipLaunchKernelGGL(fnr_batch_kernel<CLASS>, dim3(p->grid[CLASS]), dim3(kThreads), 0, stream, d,
-                       map + (size_t)CLASS * p->max_tiles, q + CLASS, 0x00010001u);
+    const uint32_t *map = reinterpret_cast<const uint32_t *>(s.dev + p->map_off) + (size_t)CLASS * p->max_tiles;
+    if (p->threads == 256)
+        hipLaunchKernelGGL((fnr_batch_kernel<CLASS, 256>), dim3(p->grid[CLASS]), dim3(256), 0, stream, d, map,
+                           q + CLASS, 0x00010001u);
+    else
+        hipLaunchKernelGGL((fnr_batch_kernel<CLASS, 128>), dim3(p->grid[CLASS]), dim3(128), 0, stream, d, map,
+                           q + CLASS, 0x00010001u);
 }
 
 void launch_batch(const irf_plan *p, const irf_plan::Set &s, unsigned classes, hipStream_t stream) {
@@ -124,8 +139,16 @@ extern "C" {
 
 int ir_filter_frame_tiles(int width, int height) {
     if (width < 1 || height < 1 || width > IRF_MAX_DIM || height > IRF_MAX_DIM) return 0;
-    return frame_tiles(width, height);
+    return frame_tiles(width, height, batch_threads_now());
 }
+
+irf_status ir_filter_set_batch_threads(int threads) {
+    if (threads != 0 && threads != 128 && threads != 256) return IRF_ERR_TUNING;
+    g_batch_threads.store(threads, std::memory_order_relaxed);
+    return IRF_OK;
+}
+
+int ir_filter_get_batch_threads(void) { return batch_threads_now(); }
 
 irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles, unsigned flags) {
     if (!plan) return IRF_ERR_NULL;
@@ -142,9 +165,16 @@ irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles,
         p->map_off = p->desc_off + sizeof(FrameDesc) * (size_t)max_frames;
         p->bytes = p->map_off + sizeof(uint32_t) * kBatchClasses * (size_t)max_tiles;
         (void)hipGetLastError();
-        p->grid[0] = batch_grid<0>();
-        p->grid[1] = batch_grid<1>();
-        p->grid[2] = batch_grid<2>();
+        p->threads = batch_threads_now();
+        if (p->threads == 256) {
+            p->grid[0] = batch_grid<0, 256>();
+            p->grid[1] = batch_grid<1, 256>();
+            p->grid[2] = batch_grid<2, 256>();
+        } else {
+            p->grid[0] = batch_grid<0, 128>();
+            p->grid[1] = batch_grid<1, 128>();
+            p->grid[2] = batch_grid<2, 128>();
+        }
         for (auto &s : p->set) {
             if (hipMalloc(&s.dev, p->bytes) != hipSuccess) {
                 free_plan(p);
@@ -210,7 +240,7 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
             const int b = bytes_of(f.dtype);
             if ((st = check_layout(f.src_pitch, 0, f.width, f.height, 1, b))) return st;
             if ((st = check_layout(f.dst_pitch, 0, f.width, f.height, 1, b))) return st;
-            tiles[batch_class(f.window)] += frame_tiles(f.width, f.height);
+            tiles[batch_class(f.window)] += frame_tiles(f.width, f.height, p->threads);
         }
         for (int c = 0; c < kBatchClasses; ++c)
             if (tiles[c] > p->max_tiles) return IRF_ERR_CAPACITY;
@@ -242,7 +272,7 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         int begin[kBatchClasses] = {};
         for (int i = 0; i < n; ++i) {
             const irf_frame &f = frames[i];
-            const int b = bytes_of(f.dtype), c = batch_class(f.window), nt = frame_tiles(f.width, f.height);
+            const int b = bytes_of(f.dtype), c = batch_class(f.window), nt = frame_tiles(f.width, f.height, p->threads);
             FrameDesc &e = d[i];
             e.src = static_cast<const uint8_t *>(f.src);
             e.dst = static_cast<uint8_t *>(f.dst);

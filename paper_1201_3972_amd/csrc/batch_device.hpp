@@ -50,11 +50,11 @@ __host__ __device__ constexpr int batch_class(int window) {
     return window <= kBatchClassMax[0] ? 0 : (window <= kBatchClassMax[1] ? 1 : 2);
 }
 
-template <typename T, int K>
+template <typename T, int K, int NT>
 __device__ __forceinline__ uint32_t batch_tile(const FrameDesc &d, int local, unsigned char *smem,
                                                uint32_t ticket, unsigned int *s_next, uint32_t pk_one) {
-    using G = Geometry<K>;
-    TileSmem<K> &sm = *reinterpret_cast<TileSmem<K> *>(smem);
+    using G = Geometry<K, NT>;
+    TileSmem<K, NT> &sm = *reinterpret_cast<TileSmem<K, NT> *>(smem);
     StackArgs a = {};
     a.src = d.src;
     a.dst = d.dst;
@@ -69,21 +69,21 @@ __device__ __forceinline__ uint32_t batch_tile(const FrameDesc &d, int local, un
     a.pk_one = pk_one;
     int f, x0, y0;
     tile_origin(a, local, G::TH, f, x0, y0);
-    load_tile<T, K>(a.src, a.src_pitch, a.width, a.height, x0, y0, a.aligned != 0, sm.tile);
+    load_tile<T, K, NT>(a.src, a.src_pitch, a.width, a.height, x0, y0, a.aligned != 0, sm.tile);
     if (threadIdx.x == 0) {
         sm.count = 0;
         *s_next = ticket;  // the loads were waited for, so the atomic has returned too
     }
     __syncthreads();
-    return process_tile<T, K, MODE_FNR>(a, local, sm);
+    return process_tile<T, K, MODE_FNR, NT>(a, local, sm);
 }
 
-template <int CLASS>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kBatchClassWaves[CLASS], 8))) void fnr_batch_kernel(const FrameDesc *descs,
+template <int CLASS, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kBatchClassWaves[CLASS], 8))) void fnr_batch_kernel(const FrameDesc *descs,
                                                              const uint32_t *tile_frame,
                                                              BatchQueue *queue, uint32_t pk_one) {
     constexpr int KMAX = kBatchClassMax[CLASS];
-    __shared__ __attribute__((aligned(16))) unsigned char smem[sizeof(TileSmem<KMAX>)];
+    __shared__ __attribute__((aligned(16))) unsigned char smem[sizeof(TileSmem<KMAX, NT>)];
     // next-tile slots alternate by iteration: thread 0 fills slot (i+1)&1 while
     // slow threads may still be reading slot i&1 after the last barrier
     __shared__ unsigned int s_next[2];
@@ -101,26 +101,26 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kBatch
         uint32_t flagged = 0;
         if constexpr (CLASS == 0) {
             switch (d.kind) {
-                case batch_kind(1, 3): flagged = batch_tile<uint8_t, 3>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 5): flagged = batch_tile<uint8_t, 5>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 7): flagged = batch_tile<uint8_t, 7>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 3): flagged = batch_tile<uint16_t, 3>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 5): flagged = batch_tile<uint16_t, 5>(d, local, smem, ticket, slot, pk_one); break;
-                default: flagged = batch_tile<uint16_t, 7>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(1, 3): flagged = batch_tile<uint8_t, 3, NT>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(1, 5): flagged = batch_tile<uint8_t, 5, NT>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(1, 7): flagged = batch_tile<uint8_t, 7, NT>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(2, 3): flagged = batch_tile<uint16_t, 3, NT>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(2, 5): flagged = batch_tile<uint16_t, 5, NT>(d, local, smem, ticket, slot, pk_one); break;
+                default: flagged = batch_tile<uint16_t, 7, NT>(d, local, smem, ticket, slot, pk_one); break;
             }
         } else if constexpr (CLASS == 1) {
             switch (d.kind) {
-                case batch_kind(1, 9): flagged = batch_tile<uint8_t, 9>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 11): flagged = batch_tile<uint8_t, 11>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 9): flagged = batch_tile<uint16_t, 9>(d, local, smem, ticket, slot, pk_one); break;
-                default: flagged = batch_tile<uint16_t, 11>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(1, 9): flagged = batch_tile<uint8_t, 9, NT>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(1, 11): flagged = batch_tile<uint8_t, 11, NT>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(2, 9): flagged = batch_tile<uint16_t, 9, NT>(d, local, smem, ticket, slot, pk_one); break;
+                default: flagged = batch_tile<uint16_t, 11, NT>(d, local, smem, ticket, slot, pk_one); break;
             }
         } else {
             switch (d.kind) {
-                case batch_kind(1, 13): flagged = batch_tile<uint8_t, 13>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 15): flagged = batch_tile<uint8_t, 15>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 13): flagged = batch_tile<uint16_t, 13>(d, local, smem, ticket, slot, pk_one); break;
-                default: flagged = batch_tile<uint16_t, 15>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(1, 13): flagged = batch_tile<uint8_t, 13, NT>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(1, 15): flagged = batch_tile<uint8_t, 15, NT>(d, local, smem, ticket, slot, pk_one); break;
+                case batch_kind(2, 13): flagged = batch_tile<uint16_t, 13, NT>(d, local, smem, ticket, slot, pk_one); break;
+                default: flagged = batch_tile<uint16_t, 15, NT>(d, local, smem, ticket, slot, pk_one); break;
             }
         }
         if (d.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)

@@ -19,13 +19,15 @@
 //               columns (two pixels per VGPR), then a van Herk / Gil-Werman
 //               sliding min/max down the R+k-1 rows;
 //   3. compact: flagged pixels of the tile go to an LDS list (wave prefix scan);
-//   4. select:  k <= 11: each lane takes two list entries and computes both
-//               medians in packed u16 registers by forgetful selection over
-//               sorted blocks merged into a sorted run whose provably-non-median
-//               ends are dropped (window rows are read as whole 32-bit words);
-//               k >= 13: each lane holds one window in registers (two values
-//               per VGPR) and bisects on grey level, counting the values above
-//               the probe (bit-by-bit value search);
+//   4. select:  networks (k <= 11): each lane takes two list entries and
+//               computes both medians in packed u16 registers by forgetful
+//               selection over sorted blocks merged into a sorted run whose
+//               provably-non-median ends are dropped (window rows are read as
+//               whole 32-bit words); bisection (any k, the default for k >= 13):
+//               each lane holds one window in registers (two values per VGPR)
+//               and bisects on grey level, counting the values above the probe
+//               (bit-by-bit value search).  Which one, and the workgroup size,
+//               come from the host's per-window tuning table;
 //   5. store:   results replace the flagged pixels in LDS, then the tile is
 //               written out with vector stores.
 #pragma once
@@ -43,11 +45,17 @@ constexpr int kThreads = 128;                // workgroup of the batch kernels
 constexpr int kTileW = 128;                  // output columns per tile
 constexpr int kThreadsX = kTileW / 4;        // 32 threads across, 4 columns each
 constexpr int kStrips = kThreads / kThreadsX;  // 4 strips of R rows
-// Workgroup of the single-size stack kernels, per window: 7x7 takes tiles of
-// twice the height, which fill its selection waves better (a 128x32 tile holds
-// about 80 window pairs to select at the usual impulse rates, just over one
-// wave's worth); the other windows run faster with the smaller tile.
-constexpr int stack_threads(int K) { return K == 7 ? 256 : 128; }
+// Selection algorithm: forgetful selection networks on two windows per lane
+// (windows up to 11x11), or grey-level bisection on one window per lane.
+enum Select : int { kSelectNetwork = 1, kSelectBisect = 2 };
+constexpr int kNetworkMaxWindow = 11;
+// Untuned choices of the stack kernels: 7x7 takes 256-thread workgroups on tiles
+// of twice the height, which fill its selection waves better (a 128x32 tile
+// holds about 80 window pairs at the usual impulse rates, just over one wave's
+// worth); the other windows run faster with the smaller tile.  The host's
+// tuning table starts from these and an autotuner may replace them.
+constexpr int default_threads(int K) { return K == 7 ? 256 : 128; }
+constexpr int default_select(int K) { return K <= kNetworkMaxWindow ? kSelectNetwork : kSelectBisect; }
 constexpr int kHalo = 8;                     // LDS columns kept left and right of the tile
 constexpr int kLdsW = kTileW + 2 * kHalo;    // 144 16-bit values staged per LDS row
 constexpr int kChunks = kLdsW / 8;           // 8-pixel load chunks per LDS row
@@ -571,9 +579,7 @@ __device__ __forceinline__ uint32_t median_pair(const uint16_t *tile, uint32_t o
     return select_blocks<K, 0, 0, (K * K - 1) / 2>(nullptr, pair_row(tile, o0, o1), win);
 }
 
-constexpr int kRegisterSelectMin = 13;
-
-// Windows of 13x13 and 15x15, one window per lane held in registers, two
+// One window per lane held in registers (the default for 13x13 and 15x15), two
 // window values per VGPR: a bisection on grey level over [g_min, g_max] counts
 // the values above the probe with three packed operations per register and
 // round (the window is read from LDS once).
@@ -700,9 +706,11 @@ struct TileSmem {
 // One tile already staged in LDS: detection, compaction of the flagged pixels,
 // selection, then the tile (flagged pixels replaced) is stored.  Returns the
 // number of flagged pixels the calling wave found (wave-uniform).
-template <typename T, int K, int MODE, int NT = kThreads>
+template <typename T, int K, int MODE, int NT = kThreads, int SEL = default_select(K)>
 __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K, NT> &sm) {
     using G = Geometry<K, NT>;
+    static_assert(SEL == kSelectBisect || (SEL == kSelectNetwork && K <= kNetworkMaxWindow),
+                  "selection networks are built for windows up to 11x11");
     constexpr int R = G::R;
     const int f = tile / a.tiles_per_frame;
     const int rem = tile - f * a.tiles_per_frame;
@@ -782,7 +790,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         //    the list rotates with the tile (waves sit on fixed SIMDs)
         constexpr int corner = G::r * kLdsPitch + G::r;
         const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)tile) % NT;
-        if constexpr (K >= kRegisterSelectMin) {
+        if constexpr (SEL == kSelectBisect) {
             // one window per lane
             for (uint32_t i = slot; i < total; i += NT) {
                 const uint32_t e0 = sm.list[i];
@@ -844,9 +852,8 @@ __device__ __forceinline__ void tile_origin(const StackArgs &a, int tile, int th
 // barriers per tile: before the LDS tile is overwritten, after it is written,
 // after the flagged list is complete and after the selection.  Other resident
 // workgroups run while one waits for its tile's loads.
-template <typename T, int K, int MODE>
-__global__ __launch_bounds__(stack_threads(K)) void fnr_persistent_kernel(StackArgs a) {
-    constexpr int NT = stack_threads(K);
+template <typename T, int K, int MODE, int NT, int SEL>
+__global__ __launch_bounds__(NT) void fnr_persistent_kernel(StackArgs a) {
     using G = Geometry<K, NT>;
     __shared__ __attribute__((aligned(16))) TileSmem<K, NT> sm;
     const TileRange rg = xcd_range(blockIdx.x, gridDim.x, a.total_tiles);
@@ -860,7 +867,7 @@ __global__ __launch_bounds__(stack_threads(K)) void fnr_persistent_kernel(StackA
                         aligned, sm.tile);
         if (threadIdx.x == 0) sm.count = 0;
         __syncthreads();
-        flagged += process_tile<T, K, MODE, NT>(a, t, sm);
+        flagged += process_tile<T, K, MODE, NT, SEL>(a, t, sm);
     }
     if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR) {
         if (a.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)

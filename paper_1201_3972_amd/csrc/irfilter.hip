@@ -7,9 +7,12 @@
 
 #include <stdint.h>
 
+#include <atomic>
+
 #include "../../include/irfilter.h"
 #include "fnr_device.hpp"
 #include "host_common.hpp"
+#include "stack_launch.hpp"
 
 namespace irf {
 namespace {
@@ -18,47 +21,25 @@ using namespace host;
 
 constexpr int kVersion = (1 << 16) | 0;
 
-int tile_rows(int window) { return stack_threads(window) / kThreadsX * Geometry<3>::R; }
+// Tuning table of the single-size kernels, per pixel type and window: 0 means
+// the untuned default, otherwise threads | select << 16.  Entries change only
+// through ir_filter_set_tuning; a launch reads its entry once.
+std::atomic<uint32_t> g_tuning[2][8];
 
-// Persistent grid: as many workgroups as fit on the device at once (never more
-// than there are tiles).
-template <typename T, int K, int MODE>
-int persistent_grid(int total_tiles) {
-    static const int per_cu = [] {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_persistent_kernel<T, K, MODE>, stack_threads(K),
-                                                         0) != hipSuccess ||
-            n < 1)
-            n = 1;
-        return n;
-    }();
-    const long long g = (long long)per_cu * device_cus();
-    return (int)(g < total_tiles ? g : total_tiles);
+int window_slot(int window) { return (window - 3) / 2; }
+
+Tuning tuning_of(irf_dtype dtype, int window) {
+    const uint32_t v = g_tuning[dtype == IRF_U8 ? 0 : 1][window_slot(window)].load(std::memory_order_relaxed);
+    if (v == 0) return default_tuning(window);
+    return {(int)(v & 0xffffu), (int)(v >> 16)};
 }
 
-template <typename T, int K, int MODE>
-void launch_t(const StackArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((fnr_persistent_kernel<T, K, MODE>), dim3(persistent_grid<T, K, MODE>(a.total_tiles)),
-                       dim3(stack_threads(K)), 0, s, a);
-}
-
-template <typename T, int MODE>
-bool launch_k(int window, const StackArgs &a, hipStream_t s) {
-    switch (window) {
-        case 3: launch_t<T, 3, MODE>(a, s); return true;
-        case 5: launch_t<T, 5, MODE>(a, s); return true;
-        case 7: launch_t<T, 7, MODE>(a, s); return true;
-        case 9: launch_t<T, 9, MODE>(a, s); return true;
-        case 11: launch_t<T, 11, MODE>(a, s); return true;
-        case 13: launch_t<T, 13, MODE>(a, s); return true;
-        case 15: launch_t<T, 15, MODE>(a, s); return true;
-        default: return false;
-    }
-}
+int tile_rows(int threads) { return threads / kThreadsX * Geometry<3>::R; }
 
 template <int MODE>
 irf_status launch(irf_dtype dtype, int window, int nframes, StackArgs a, hipStream_t s) {
-    const int th = tile_rows(window);
+    const Tuning t = tuning_of(dtype, window);
+    const int th = tile_rows(t.threads);
     a.tiles_x = (a.width + kTileW - 1) / kTileW;
     const int tiles_y = (a.height + th - 1) / th;
     const uint64_t per_frame = (uint64_t)a.tiles_x * (uint64_t)tiles_y;
@@ -68,8 +49,8 @@ irf_status launch(irf_dtype dtype, int window, int nframes, StackArgs a, hipStre
     a.total_tiles = (int)total;
     a.pk_one = 0x00010001u;
     (void)hipGetLastError();
-    bool ok = dtype == IRF_U8 ? launch_k<uint8_t, MODE>(window, a, s)
-                              : launch_k<uint16_t, MODE>(window, a, s);
+    const bool ok = dtype == IRF_U8 ? launch_stack_u8(window, MODE, t, a, s)
+                                    : launch_stack_u16(window, MODE, t, a, s);
     if (!ok) return IRF_ERR_WINDOW;
     if (hipGetLastError() != hipSuccess) return IRF_ERR_HIP;
     return IRF_OK;
@@ -250,10 +231,33 @@ const char *ir_filter_status_string(irf_status s) {
         case IRF_ERR_HIP: return "HIP error";
         case IRF_ERR_NOMEM: return "out of memory";
         case IRF_ERR_CAPACITY: return "batch exceeds plan capacity";
+        case IRF_ERR_TUNING: return "no kernel for that workgroup size and selection algorithm";
     }
     return "unknown status";
 }
 
 int ir_filter_version(void) { return kVersion; }
+
+irf_status ir_filter_get_tuning(irf_dtype dtype, int window, int *threads, int *select) {
+    if (!threads || !select) return IRF_ERR_NULL;
+    if (dtype != IRF_U8 && dtype != IRF_U16) return IRF_ERR_DTYPE;
+    if (window < 3 || window > IRF_MAX_WINDOW || (window & 1) == 0) return IRF_ERR_WINDOW;
+    const Tuning t = tuning_of(dtype, window);
+    *threads = t.threads;
+    *select = t.select;
+    return IRF_OK;
+}
+
+irf_status ir_filter_set_tuning(irf_dtype dtype, int window, int threads, int select) {
+    if (dtype != IRF_U8 && dtype != IRF_U16) return IRF_ERR_DTYPE;
+    if (window < 3 || window > IRF_MAX_WINDOW || (window & 1) == 0) return IRF_ERR_WINDOW;
+    uint32_t v = 0;  // threads = select = 0 restores the default
+    if (threads != 0 || select != 0) {
+        if (!tuning_available(window, {threads, select})) return IRF_ERR_TUNING;
+        v = (uint32_t)threads | ((uint32_t)select << 16);
+    }
+    g_tuning[dtype == IRF_U8 ? 0 : 1][window_slot(window)].store(v, std::memory_order_relaxed);
+    return IRF_OK;
+}
 
 }  // extern "C"

@@ -1,0 +1,114 @@
+// stack_launch.hpp -- host launch of the single-size (frame and stack) kernels
+// by window, mode, workgroup size and selection algorithm.  The kernels of each
+// pixel type are instantiated in their own translation unit (stack_u8.hip,
+// stack_u16.hip), so the two compile in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fnr_device.hpp"
+#include "host_common.hpp"
+
+namespace irf {
+
+// One tuning-table entry: workgroup size (128 or 256 threads, i.e. tiles of
+// 128x32 or 128x64 pixels) and selection algorithm (Select).
+struct Tuning {
+    int threads;
+    int select;
+};
+
+inline Tuning default_tuning(int window) { return {default_threads(window), default_select(window)}; }
+
+// Whether a kernel exists for (window, tuning): 128 or 256 threads; networks
+// for windows up to 11x11, bisection for every window.
+inline bool tuning_available(int window, Tuning t) {
+    if (t.threads != 128 && t.threads != 256) return false;
+    if (t.select == kSelectNetwork) return window <= kNetworkMaxWindow;
+    return t.select == kSelectBisect;
+}
+
+// Launch the stack kernel of the pixel type for a.total_tiles tiles; false if
+// the combination has no kernel (nothing is launched then).
+bool launch_stack_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
+bool launch_stack_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
+
+namespace stack_impl {
+
+// Persistent grid: as many workgroups as fit on the device at once (never more
+// than there are tiles).
+template <typename T, int K, int MODE, int NT, int SEL>
+int persistent_grid(int total_tiles) {
+    static const int per_cu = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_persistent_kernel<T, K, MODE, NT, SEL>, NT,
+                                                         0) != hipSuccess ||
+            n < 1)
+            n = 1;
+        return n;
+    }();
+    const long long g = (long long)per_cu * host::device_cus();
+    return (int)(g < total_tiles ? g : total_tiles);
+}
+
+template <typename T, int K, int MODE, int NT, int SEL>
+void launch_variant(const StackArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((fnr_persistent_kernel<T, K, MODE, NT, SEL>),
+                       dim3(persistent_grid<T, K, MODE, NT, SEL>(a.total_tiles)), dim3(NT), 0, s, a);
+}
+
+// Detection selects nothing: its kernels exist per workgroup size only.
+template <typename T, int K, int MODE, int NT>
+bool launch_threads(int select, const StackArgs &a, hipStream_t s) {
+    if constexpr (MODE == MODE_DETECT) {
+        launch_variant<T, K, MODE, NT, default_select(K)>(a, s);
+        return true;
+    } else {
+        if (select == kSelectBisect) {
+            launch_variant<T, K, MODE, NT, kSelectBisect>(a, s);
+            return true;
+        }
+        if constexpr (K <= kNetworkMaxWindow) {
+            if (select == kSelectNetwork) {
+                launch_variant<T, K, MODE, NT, kSelectNetwork>(a, s);
+                return true;
+            }
+        }
+        return false;
+    }
+}
+
+template <typename T, int K, int MODE>
+bool launch_tuned(Tuning t, const StackArgs &a, hipStream_t s) {
+    if (t.threads == 128) return launch_threads<T, K, MODE, 128>(t.select, a, s);
+    if (t.threads == 256) return launch_threads<T, K, MODE, 256>(t.select, a, s);
+    return false;
+}
+
+template <typename T, int MODE>
+bool launch_window(int window, Tuning t, const StackArgs &a, hipStream_t s) {
+    switch (window) {
+        case 3: return launch_tuned<T, 3, MODE>(t, a, s);
+        case 5: return launch_tuned<T, 5, MODE>(t, a, s);
+        case 7: return launch_tuned<T, 7, MODE>(t, a, s);
+        case 9: return launch_tuned<T, 9, MODE>(t, a, s);
+        case 11: return launch_tuned<T, 11, MODE>(t, a, s);
+        case 13: return launch_tuned<T, 13, MODE>(t, a, s);
+        case 15: return launch_tuned<T, 15, MODE>(t, a, s);
+        default: return false;
+    }
+}
+
+template <typename T>
+bool launch_stack(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s) {
+    switch (mode) {
+        case MODE_DETECT: return launch_window<T, MODE_DETECT>(window, t, a, s);
+        case MODE_FNR: return launch_window<T, MODE_FNR>(window, t, a, s);
+        case MODE_MEDIAN_MASK: return launch_window<T, MODE_MEDIAN_MASK>(window, t, a, s);
+        case MODE_MEDIAN_ALL: return launch_window<T, MODE_MEDIAN_ALL>(window, t, a, s);
+        default: return false;
+    }
+}
+
+}  // namespace stack_impl
+}  // namespace irf

@@ -1,0 +1,8 @@
+// stack_u8.hip -- the 8-bit instantiations of the single-size kernels.
+#include "stack_launch.hpp"
+
+namespace irf {
+bool launch_stack_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s) {
+    return stack_impl::launch_stack<uint8_t>(window, mode, t, a, s);
+}
+}  // namespace irf

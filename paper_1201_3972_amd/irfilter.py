@@ -27,7 +27,7 @@ IRF_U16 = 2
 STATUS = {
     0: "IRF_OK", -1: "IRF_ERR_NULL", -2: "IRF_ERR_DIMS", -3: "IRF_ERR_PITCH", -4: "IRF_ERR_DTYPE",
     -5: "IRF_ERR_WINDOW", -6: "IRF_ERR_PASSES", -7: "IRF_ERR_ALIAS", -8: "IRF_ERR_HIP",
-    -9: "IRF_ERR_NOMEM", -10: "IRF_ERR_CAPACITY",
+    -9: "IRF_ERR_NOMEM", -10: "IRF_ERR_CAPACITY", -11: "IRF_ERR_TUNING",
 }
 
 # name -> (restype, argtypes); mirrors include/irfilter.h
@@ -44,7 +44,15 @@ SIGNATURES = {
     "ir_filter_frame_tiles": (_i32, [_i32, _i32]),
     "ir_filter_status_string": (ctypes.c_char_p, [_i32]),
     "ir_filter_version": (_i32, []),
+    "ir_filter_get_tuning": (_i32, [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "ir_filter_set_tuning": (_i32, [_i32, _i32, _i32, _i32]),
+    "ir_filter_set_batch_threads": (_i32, [_i32]),
+    "ir_filter_get_batch_threads": (_i32, []),
 }
+
+IRF_SELECT_NETWORK = 1
+IRF_SELECT_BISECT = 2
+SELECT_NAMES = {IRF_SELECT_NETWORK: "network", IRF_SELECT_BISECT: "bisect"}
 
 
 IRF_PLAN_GRAPH = 1
@@ -195,6 +203,38 @@ def ir_filter_run_frames(src, dst, window: int, passes: int = 1, scratch=None, f
 
 def version() -> int:
     return load().ir_filter_version()
+
+
+def _dtype_arg(dtype) -> int:
+    if dtype in (IRF_U8, IRF_U16):
+        return dtype
+    if dtype in ("u8", "uint8"):
+        return IRF_U8
+    if dtype in ("u16", "uint16"):
+        return IRF_U16
+    raise ValueError(f"pixel type {dtype!r}: use 'u8', 'u16', IRF_U8 or IRF_U16")
+
+
+def get_tuning(dtype, window: int):
+    """(threads, select) used by the single-size entry points for this pixel type and window."""
+    t, sel = ctypes.c_int(), ctypes.c_int()
+    _check("ir_filter_get_tuning", load().ir_filter_get_tuning(_dtype_arg(dtype), window, ctypes.byref(t),
+                                                               ctypes.byref(sel)))
+    return t.value, sel.value
+
+
+def set_tuning(dtype, window: int, threads: int, select: int) -> None:
+    """Set (threads, select) for a pixel type and window; (0, 0) restores the default."""
+    _check("ir_filter_set_tuning", load().ir_filter_set_tuning(_dtype_arg(dtype), window, threads, select))
+
+
+def set_batch_threads(threads: int) -> None:
+    """Workgroup size of batch plans created from now on (128, 256, or 0 for the default)."""
+    _check("ir_filter_set_batch_threads", load().ir_filter_set_batch_threads(threads))
+
+
+def get_batch_threads() -> int:
+    return load().ir_filter_get_batch_threads()
 
 
 def frame_tiles(width: int, height: int) -> int:

@@ -191,10 +191,9 @@ int ir_filter_frame_tiles(int width, int height);
  * per pixel type and window, the workgroup size (128 threads on tiles of
  * 128x32 pixels, or 256 threads on 128x64) and the selection algorithm:
  *   IRF_SELECT_NETWORK  forgetful selection networks, two windows per lane
- *                       (windows up to 11x11)
  *   IRF_SELECT_BISECT   grey-level bisection, one window per lane (any window)
- * Untuned defaults: 128 threads except 256 for 7x7; networks up to 11x11,
- * bisection for 13x13 and 15x15.  ir_filter_set_tuning(dtype, window, 0, 0)
+ * Untuned defaults: 128 threads except 256 for 7x7, networks for every window.
+ * ir_filter_set_tuning(dtype, window, 0, 0)
  * restores the default; an unavailable combination returns IRF_ERR_TUNING.
  * The autotuner of the Python package measures the choices and sets them.
  */

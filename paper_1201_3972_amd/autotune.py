@@ -31,7 +31,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(PKG, "tuning")
 WINDOWS = (3, 5, 7, 9, 11, 13, 15)
 SELECT_BY_NAME = {"network": irfilter.IRF_SELECT_NETWORK, "bisect": irfilter.IRF_SELECT_BISECT}
-NETWORK_MAX_WINDOW = 11
+NETWORK_MAX_WINDOW = 15
 
 
 def candidates(window: int) -> List[Tuple[int, int]]:

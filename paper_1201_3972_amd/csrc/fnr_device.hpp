@@ -222,12 +222,77 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
 // ---------------------------------------------------------------------------
 // 2. detection: separable window min / max on packed pairs
 // ---------------------------------------------------------------------------
+// Half swaps and broadcasts fold into the op_sel fields of the packed min/max.
+__device__ __forceinline__ u16x2 as_pair(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t both_min(uint32_t x) {  // min of the halves, in both halves
+    const u16x2 v = as_pair(x);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(v, __builtin_shufflevector(v, v, 1, 0)));
+}
+__device__ __forceinline__ uint32_t both_max(uint32_t x) {
+    const u16x2 v = as_pair(x);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, __builtin_shufflevector(v, v, 1, 0)));
+}
+__device__ __forceinline__ uint32_t hi_lo(uint32_t a, uint32_t b) {  // (a.hi, b.lo)
+    return __builtin_bit_cast(uint32_t, __builtin_shufflevector(as_pair(a), as_pair(b), 1, 2));
+}
+
 // Horizontal min/max over k columns for the thread's 4 output columns of one
 // LDS row.  `p` points at the thread's first output column.  Outputs: packed
-// pair 0 = columns (0,1), pair 1 = columns (2,3).
+// pair 0 = columns (0,1), pair 1 = columns (2,3); c0, c1 = the centre pairs.
+//
+// Odd radius r = 2m+1: with E_j the aligned pair (columns 2j, 2j+1), output
+// column 0 takes columns -r..r and column 1 takes -r+1..r+1.  Both contain the
+// r whole pairs E_-m..E_m; their min over both halves (a packed min with the
+// halves swapped) plus the one column each still lacks, -r for column 0 and
+// r+1 for column 1, packed into one pair, gives pair 0.  Pair 1 is the same two
+// columns further right, and shares E_-m+1..E_m with pair 0.  No odd-aligned
+// pair is ever formed.
+template <int r>
+__device__ __forceinline__ void row_minmax_odd(const uint16_t *p, uint32_t &mn0, uint32_t &mn1,
+                                               uint32_t &mx0, uint32_t &mx1, uint32_t &c0, uint32_t &c1) {
+    constexpr int m = (r - 1) / 2;
+    constexpr int JLO = (-m - 1) & ~1, JHI = (m + 2) | 1;  // whole aligned 8-byte words
+    constexpr int NJ = JHI - JLO + 1;
+    const uint2 *q = reinterpret_cast<const uint2 *>(p);
+    uint32_t D[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; j += 2) {
+        const uint2 w = q[(j + JLO) / 2];
+        D[j] = w.x;
+        D[j + 1] = w.y;
+    }
+    auto E = [&](int j) -> uint32_t { return D[j - JLO]; };
+    uint32_t a_mn = E(0), a_mx = E(0), b_mn = E(1), b_mx = E(1);
+    if constexpr (m > 0) {
+        uint32_t smn = E(1 - m), smx = smn;  // E_-m+1 .. E_m, shared by both pairs
+#pragma unroll
+        for (int j = 2 - m; j <= m; ++j) {
+            smn = pk_min(smn, E(j));
+            smx = pk_max(smx, E(j));
+        }
+        a_mn = pk_min(smn, E(-m));
+        a_mx = pk_max(smx, E(-m));
+        b_mn = pk_min(smn, E(m + 1));
+        b_mx = pk_max(smx, E(m + 1));
+    }
+    const uint32_t p0 = hi_lo(E(-m - 1), E(m + 1)), p1 = hi_lo(E(-m), E(m + 2));
+    mn0 = pk_min(both_min(a_mn), p0);
+    mx0 = pk_max(both_max(a_mx), p0);
+    mn1 = pk_min(both_min(b_mn), p1);
+    mx1 = pk_max(both_max(b_mx), p1);
+    c0 = E(0);
+    c1 = E(1);
+}
+
+// Even radius and 3x3: the shared middle offsets with odd-aligned pairs built by
+// byte alignment (at 3x3 this measured faster than the odd-radius form).
 template <int r>
 __device__ __forceinline__ void row_minmax(const uint16_t *p, uint32_t &mn0, uint32_t &mn1,
                                            uint32_t &mx0, uint32_t &mx1, uint32_t &c0, uint32_t &c1) {
+    if constexpr ((r & 1) && r >= 3) {
+        row_minmax_odd<r>(p, mn0, mn1, mx0, mx1, c0, c1);
+        return;
+    }
     // pairs JLO..JHI cover columns -r .. 3+r; the range is widened to whole
     // 8-byte words so every LDS read is aligned
     constexpr int JLO = (-((r + 1) / 2)) & ~1;

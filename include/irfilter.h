@@ -180,6 +180,88 @@ void ir_filter_plan_destroy(irf_plan *plan);
  * the current batch tuning. */
 int ir_filter_frame_tiles(int width, int height);
 
+/* Tiles of one frame as counted against this plan's max_tiles (0 for a NULL
+ * plan or a size outside 1..IRF_MAX_DIM). */
+int ir_filter_plan_frame_tiles(const irf_plan *plan, int width, int height);
+
+/*
+ * Serving: a continuous-batching request loop over frames in pinned host
+ * memory (the batched FNR filter of ir_filter_run_batch, one pass per frame).
+ * Not part of the paper's method; it serves its filter to a stream of
+ * requests.
+ *
+ * Each step admits arrived requests while device memory allows (frames of a
+ * registered video stream use that stream's resident device slots, kept for
+ * the server's lifetime; other frames take two blocks from a bounded device
+ * arena, released when their result has reached the host), copies them host
+ * -> device on one copy stream, filters them with ONE batched launch on a
+ * compute stream, and copies the results back on a second copy stream, events
+ * ordering the three (the two copy directions overlap).  Up to max_inflight steps are on the device at once, so
+ * copies of one step overlap the kernels of another.  A request completes when
+ * its device -> host copy has finished; its latency is completion time minus
+ * its arrival time, both on the server's clock (seconds since creation).
+ *
+ * irf_request: one frame.  host_src / host_dst are pinned host buffers
+ * (hipHostMalloc, torch pin_memory) owned by the caller, which must keep them
+ * until the request completes; pitches are in bytes; stream_id is a
+ * registered stream or -1; arrival is on the server's clock, and a request is
+ * not admitted before it.  The server is not thread-safe.
+ */
+typedef struct irf_server irf_server;
+
+typedef struct {
+    uint64_t id;
+    const void *host_src;
+    void *host_dst;
+    size_t src_pitch, dst_pitch;
+    int width, height;
+    irf_dtype dtype;
+    int window;
+    int stream_id;
+    double arrival;
+} irf_request;
+
+/* arena_bytes: device memory for one-off frames (two blocks of W*H*b each,
+ * rounded to 4 KiB); max_batch_frames / max_batch_tiles: limits of one step;
+ * max_inflight: steps on the device at once (1..8); flags: IRF_PLAN_GRAPH. */
+irf_status ir_filter_server_create(irf_server **server, size_t arena_bytes, int max_batch_frames,
+                                   int max_batch_tiles, int max_inflight, unsigned flags);
+
+/* Give a video stream `depth` resident device slots (input + output) of its
+ * frame size and type; a frame of the stream takes any free slot, so up to
+ * `depth` consecutive frames of it can be in flight. */
+irf_status ir_filter_server_register_stream(irf_server *server, int stream_id, int width, int height,
+                                            irf_dtype dtype, int depth);
+
+/* Queue n requests (descriptors are copied).  They must come in
+ * non-decreasing arrival order, also across calls (IRF_ERR_DIMS otherwise);
+ * each is validated as in ir_filter_run_batch and must fit the arena or its
+ * stream's slots (IRF_ERR_CAPACITY otherwise: it could never be admitted). */
+irf_status ir_filter_server_submit(irf_server *server, const irf_request *requests, int n);
+
+/* One engine iteration: retire finished steps, then issue a new one if there
+ * is room and arrived work fits.  Returns 1 on progress, 0 if none, or a
+ * negative irf_status. */
+int ir_filter_server_poll(irf_server *server);
+
+/* Serve until every submitted request has completed (sleeps briefly while
+ * waiting for arrivals or completions). */
+irf_status ir_filter_server_run(irf_server *server);
+
+/* Move up to max completions (request id, latency in seconds) out of the
+ * server, oldest first; returns how many were written. */
+int ir_filter_server_completed(irf_server *server, uint64_t *ids, double *latency_s, int max);
+
+/* Seconds since the server was created (its clock), its step count, and the
+ * arena bytes held by requests in flight. */
+double ir_filter_server_now(const irf_server *server);
+int ir_filter_server_steps(const irf_server *server);
+size_t ir_filter_server_arena_used(const irf_server *server);
+
+/* Waits for outstanding steps, then releases every device and host resource.
+ * NULL is ignored. */
+void ir_filter_server_destroy(irf_server *server);
+
 /*
  * Tuning.  Not part of the method: these choices change the speed of a call,
  * never its result (every combination computes the same order statistic and

@@ -150,6 +150,11 @@ irf_status ir_filter_set_batch_threads(int threads) {
 
 int ir_filter_get_batch_threads(void) { return batch_threads_now(); }
 
+int ir_filter_plan_frame_tiles(const irf_plan *plan, int width, int height) {
+    if (!plan || width < 1 || height < 1 || width > IRF_MAX_DIM || height > IRF_MAX_DIM) return 0;
+    return frame_tiles(width, height, plan->threads);
+}
+
 irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles, unsigned flags) {
     if (!plan) return IRF_ERR_NULL;
     *plan = nullptr;

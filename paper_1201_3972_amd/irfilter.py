@@ -48,6 +48,17 @@ SIGNATURES = {
     "ir_filter_set_tuning": (_i32, [_i32, _i32, _i32, _i32]),
     "ir_filter_set_batch_threads": (_i32, [_i32]),
     "ir_filter_get_batch_threads": (_i32, []),
+    "ir_filter_plan_frame_tiles": (_i32, [_vp, _i32, _i32]),
+    "ir_filter_server_create": (_i32, [ctypes.POINTER(ctypes.c_void_p), _sz, _i32, _i32, _i32, ctypes.c_uint]),
+    "ir_filter_server_register_stream": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32]),
+    "ir_filter_server_submit": (_i32, [_vp, _vp, _i32]),
+    "ir_filter_server_poll": (_i32, [_vp]),
+    "ir_filter_server_run": (_i32, [_vp]),
+    "ir_filter_server_completed": (_i32, [_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), _i32]),
+    "ir_filter_server_now": (ctypes.c_double, [_vp]),
+    "ir_filter_server_steps": (_i32, [_vp]),
+    "ir_filter_server_arena_used": (_sz, [_vp]),
+    "ir_filter_server_destroy": (None, [_vp]),
 }
 
 IRF_SELECT_NETWORK = 1
@@ -63,6 +74,14 @@ class IrfFrame(ctypes.Structure):
     _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p), ("src_pitch", ctypes.c_size_t),
                 ("dst_pitch", ctypes.c_size_t), ("width", ctypes.c_int), ("height", ctypes.c_int),
                 ("dtype", ctypes.c_int), ("window", ctypes.c_int)]
+
+
+class IrfRequest(ctypes.Structure):
+    """Mirror of ``irf_request``."""
+    _fields_ = [("id", ctypes.c_uint64), ("host_src", ctypes.c_void_p), ("host_dst", ctypes.c_void_p),
+                ("src_pitch", ctypes.c_size_t), ("dst_pitch", ctypes.c_size_t), ("width", ctypes.c_int),
+                ("height", ctypes.c_int), ("dtype", ctypes.c_int), ("window", ctypes.c_int),
+                ("stream_id", ctypes.c_int), ("arrival", ctypes.c_double)]
 
 
 class LibraryNotBuilt(ImportError):

@@ -40,7 +40,7 @@ def test_results_in_the_mix_equal_results_alone(dev):
     srv.run_until_idle()
     srv.close()
     assert len(srv.completed) == len(reqs)
-    assert max(srv.batch_sizes) > 1  # requests were batched together
+    assert srv.steps < len(reqs)  # requests were batched together
     cache = {}
     for r in reqs:
         key = (r.host_src.data_ptr(), r.window)
@@ -72,7 +72,7 @@ def test_memory_budget_serialises_large_frames(dev):
     srv.run_until_idle()
     srv.close()
     assert len(srv.completed) == len(reqs)
-    assert srv.arena.used == 0
+    assert srv.arena_used == 0
     ref = {}
     for r in large:
         key = (r.host_src.data_ptr(), r.window)

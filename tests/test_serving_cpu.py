@@ -1,46 +1,20 @@
-"""Host-side serving logic that needs no GPU: the device-memory arena and the
-arrival process (the arena is exercised on a CPU buffer)."""
+"""Host-side serving logic that needs no GPU: the arrival process and the
+native engine's argument checks (which run before any HIP call)."""
+
+import ctypes
 
 import numpy as np
-import torch
+import pytest
 
-from paper_1201_3972_amd import serving
-
-
-def test_arena_first_fit_and_coalescing():
-    a = serving.DeviceArena(torch, 64 * 4096, "cpu")
-    x = a.alloc(4096 * 10)
-    y = a.alloc(100)            # rounds up to one page
-    z = a.alloc(4096 * 20)
-    assert (x, y, z) == (0, 40960, 45056)
-    assert a.alloc(4096 * 40) is None  # only 33 pages left
-    a.release(y, 100)
-    assert a.alloc(4096) == 40960       # first fit reuses the hole
-    a.release(40960, 4096)
-    a.release(x, 4096 * 10)
-    a.release(z, 4096 * 20)
-    assert a.free == [(0, 64 * 4096)] and a.used == 0
+from paper_1201_3972_amd import irfilter, serving
 
 
-def test_arena_random_alloc_release_never_overlaps():
-    rng = np.random.default_rng(1)
-    a = serving.DeviceArena(torch, 1 << 22, "cpu")
-    live = {}
-    for step in range(2000):
-        if live and (rng.random() < 0.45 or len(live) > 40):
-            off = list(live)[int(rng.integers(len(live)))]
-            a.release(off, live.pop(off))
-        else:
-            n = int(rng.integers(1, 1 << 17))
-            off = a.alloc(n)
-            if off is not None:
-                live[off] = n
-        spans = sorted((o, o + serving._round(n)) for o, n in live.items())
-        assert all(spans[i][1] <= spans[i + 1][0] for i in range(len(spans) - 1))
-        assert a.used == sum(serving._round(n) for n in live.values())
-    for off, n in list(live.items()):
-        a.release(off, n)
-    assert a.free == [(0, a.capacity)]
+@pytest.fixture(scope="module")
+def lib():
+    try:
+        return irfilter.load()
+    except irfilter.LibraryNotBuilt:
+        pytest.skip("library not built")
 
 
 def test_poisson_arrivals_rate():
@@ -48,3 +22,34 @@ def test_poisson_arrivals_rate():
     t = serving.poisson_arrivals(rng, 30.0, 200.0)
     assert np.all(np.diff(t) > 0) and t[-1] < 200.0
     assert abs(len(t) / 200.0 - 30.0) < 1.5
+
+
+def test_frame_bytes_and_rounding():
+    assert serving.frame_bytes(640, 512, "u16") == 655360
+    assert serving.frame_bytes(320, 240, "u8") == 76800
+    assert serving._round(1) == 4096 and serving._round(4096) == 4096 and serving._round(4097) == 8192
+
+
+def test_server_argument_checks(lib):
+    ptr = ctypes.c_void_p()
+    assert lib.ir_filter_server_create(None, 1 << 20, 8, 64, 2, 0) == -1
+    assert lib.ir_filter_server_create(ctypes.byref(ptr), 1 << 20, 0, 64, 2, 0) == -2
+    assert lib.ir_filter_server_create(ctypes.byref(ptr), 1 << 20, 8, 0, 2, 0) == -2
+    assert lib.ir_filter_server_create(ctypes.byref(ptr), 1 << 20, 8, 64, 0, 0) == -2
+    assert lib.ir_filter_server_create(ctypes.byref(ptr), 1 << 20, 8, 64, 9, 0) == -2
+    assert ptr.value is None
+    assert lib.ir_filter_server_register_stream(None, 0, 640, 512, 2, 2) == -1
+    assert lib.ir_filter_server_submit(None, None, 0) == -1
+    assert lib.ir_filter_server_poll(None) == -1
+    assert lib.ir_filter_server_run(None) == -1
+    assert lib.ir_filter_server_completed(None, None, None, 4) == 0
+    assert lib.ir_filter_server_now(None) == 0.0
+    assert lib.ir_filter_server_steps(None) == 0
+    assert lib.ir_filter_server_arena_used(None) == 0
+    lib.ir_filter_server_destroy(None)  # ignored
+
+
+def test_request_struct_matches_the_header():
+    # irf_request: u64, 2 pointers, 2 size_t, 5 ints, double (8-byte aligned)
+    assert ctypes.sizeof(irfilter.IrfRequest) == 8 + 16 + 16 + 20 + 4 + 8
+    assert irfilter.IrfRequest.arrival.offset == 64

@@ -111,6 +111,8 @@ def ingest_counters(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out_path=TRAFF
 
 def to_dev(torch, a, dev):
     a = np.ascontiguousarray(a)
+    if a.dtype == np.uint8:
+        return torch.from_numpy(a).to(dev)
     return torch.from_numpy(a.view(np.int16)).to(dev).view(torch.uint16)
 
 
@@ -315,6 +317,64 @@ def section_f3(torch, irfilter, synth, oracle, dev) -> dict:
     return out
 
 
+def section_f1(torch, irfilter, synth, oracle, dev, rounds: int = 5, reps: int = 5) -> dict:
+    """Two passes (the paper applies FNR twice, Section 4) as separate launches
+    against the fused two-pass kernel, on the 640x512 u16 stack at 5x5 and 7x7
+    and on a stack of 320x240 u8 frames at 3x3 and 5x5.  Both forms are checked
+    against the oracle's two passes on sample frames and against each other on
+    the whole stack; times are the best of interleaved rounds."""
+    cases = [("u16", 640, 512, 1024, (5, 7),
+              [synth.c2_spec(d, j) for j, d in enumerate((0.1, 0.3, 0.6))]),
+             ("u8", 320, 240, 2048, (3, 5),
+              [synth.FrameSpec(320, 240, "u8", "sp", d, 0.0, synth.config_seed(7, j))
+               for j, d in enumerate((0.2, 0.3))])]
+    out = {"workload": "two FNR passes per frame over a resident stack; fused = pairs of passes in one launch "
+                       "(overlapping 120-column tiles, pass 1 kept in LDS)", "cases": {}}
+    for dt, W, H, n, windows, specs in cases:
+        pool = [synth.make_frame(sp) for sp in specs]
+        src = torch.empty((n, H, W), dtype=torch.uint16 if dt == "u16" else torch.uint8, device=dev)
+        pool_dev = [to_dev(torch, f, dev) for f in pool]
+        for i in range(n):
+            src[i].copy_(pool_dev[i % len(pool)])
+        dst, ref, scr = torch.empty_like(src), torch.empty_like(src), torch.empty_like(src)
+        same = (lambda x, y: torch.equal(x.view(torch.int16), y.view(torch.int16))) if dt == "u16" else torch.equal
+        for k in windows:
+            before = irfilter.get_fusion(dt, k)
+            best = {}
+            try:
+                irfilter.set_fusion(dt, k, 0)
+                irfilter.ir_filter_run_frames(src, ref, k, passes=2, scratch=scr)
+                torch.cuda.synchronize()
+                for j, f in enumerate(pool):
+                    want = oracle.fnr(f, k, 2)[0]
+                    got = ref[j].view(torch.int16).cpu().numpy().view(np.uint16) if dt == "u16" else ref[j].cpu().numpy()
+                    if not np.array_equal(got, want):
+                        raise RuntimeError(f"f1 {dt} {k}x{k}: separate passes differ from the oracle")
+                for t in (256, 512):
+                    irfilter.set_fusion(dt, k, t)
+                    irfilter.ir_filter_run_frames(src, dst, k, passes=2, scratch=scr)
+                    torch.cuda.synchronize()
+                    if not same(dst, ref):
+                        raise RuntimeError(f"f1 {dt} {k}x{k}: fused ({t} threads) differs from separate passes")
+                best = {t: float("inf") for t in (0, 256, 512)}
+                for _ in range(rounds):
+                    for t in best:
+                        irfilter.set_fusion(dt, k, t)
+                        best[t] = min(best[t], _timed(torch, lambda: irfilter.ir_filter_run_frames(
+                            src, dst, k, passes=2, scratch=scr), reps))
+            finally:
+                irfilter.set_fusion(dt, k, before)
+            mpx = n * W * H / 1e6
+            out["cases"][f"{dt} {W}x{H} x{n} k={k}"] = {
+                "separate_ms": round(best[0], 4), "fused256_ms": round(best[256], 4),
+                "fused512_ms": round(best[512], 4),
+                "separate_mpx_per_s": round(mpx / best[0] * 1e3, 1),
+                "fused_best_mpx_per_s": round(mpx / min(best[256], best[512]) * 1e3, 1),
+                "fused_over_separate": round(best[0] / min(best[256], best[512]), 3)}
+            log(f"f1 {dt} {k}x{k}: {out['cases'][f'{dt} {W}x{H} x{n} k={k}']}")
+    return out
+
+
 def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
     sections = {}
     wanted = [x for x in args.sections.split(",") if x and x != "none"]
@@ -329,6 +389,8 @@ def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
         elif name == "c5":
             from paper_1201_3972_amd import serving
             sections["c5_serving"] = section_c5(torch, serving, dev)
+        elif name == "f1":
+            sections["f1_fused_two_passes"] = section_f1(torch, irfilter, synth, oracle, dev)
         elif name == "f3":
             sections["f3_table1_analogue"] = section_f3(torch, irfilter, synth, oracle, dev)
         log(f"section {name}: {time.perf_counter() - t1:.1f}s")
@@ -346,7 +408,7 @@ def main() -> int:
     ap.add_argument("--no-per-frame", action="store_true", help="skip the per-frame launch baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--sections", default="c1,c3,c4,c5,f3",
+    ap.add_argument("--sections", default="c1,c3,c4,c5,f1,f3",
                     help="extra workloads reported beside the headline (comma list, or 'none')")
     ap.add_argument("--no-headline", action="store_true",
                     help="run only the --sections workloads (for profiling them) and print their JSON")

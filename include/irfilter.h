@@ -284,6 +284,33 @@ typedef enum { IRF_SELECT_NETWORK = 1, IRF_SELECT_BISECT = 2 } irf_select;
 irf_status ir_filter_get_tuning(irf_dtype dtype, int window, int *threads, int *select);
 irf_status ir_filter_set_tuning(irf_dtype dtype, int window, int threads, int select);
 
+/* Fusion of passes (ir_filter_run / ir_filter_run_frames with passes >= 2;
+ * Section 4 applies the filter twice).  With fusion on, each pair of passes
+ * runs as one launch: a tile gets pass 1 in LDS and pass 2 reads those results
+ * there, so the intermediate frame never goes to memory; an odd last pass
+ * runs on its own.  Results and per-pass counts equal those of separate
+ * passes exactly.  Per pixel type and window:
+ *   threads  0         every pass is its own launch
+ *            256, 512  fused, workgroups of that size (blocks of 128x64 or
+ *                      128x128 pixels, of which 120 x (64 or 128 - window + 1)
+ *                      are output; the rest is recomputed by neighbours)
+ *            -1        automatic, the default: per call, the fused size whose
+ *                      tiles cover the fewest pixels if they cover no more than
+ *                      the tiles of two separate passes, else separate passes
+ *                      (both kernels are bound by ALU work per covered pixel,
+ *                      so fusion pays where its overlap costs nothing: 320x240
+ *                      frames fuse, 640x512 and 1920x1080 frames do not)
+ * Fused kernels exist for windows up to 9x9 (IRF_ERR_TUNING otherwise; -1
+ * and 0 are accepted for every window).  The table is process-wide like the
+ * one above. */
+irf_status ir_filter_get_fusion(irf_dtype dtype, int window, int *threads);
+irf_status ir_filter_set_fusion(irf_dtype dtype, int window, int threads);
+
+/* The choice ir_filter_run makes for two or more passes over a width x height
+ * frame of this type and window under the current settings: 0 (separate
+ * passes) or the fused workgroup size. */
+irf_status ir_filter_resolve_fusion(irf_dtype dtype, int window, int width, int height, int *threads);
+
 /* Batch workgroup size for plans created from now on: 128 (tiles of 128x32,
  * the default) or 256 (128x64); 0 restores the default.  Other values return
  * IRF_ERR_TUNING. */

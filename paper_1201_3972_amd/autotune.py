@@ -1,6 +1,7 @@
 """Autotuner: per pixel type and window, measure every (workgroup size,
 selection algorithm) the library has a kernel for, and keep the fastest; for
-batches, measure the batch workgroup size.
+two-pass runs, whether pairs of passes run fused (and with which workgroup
+size) or as separate launches; for batches, the batch workgroup size.
 
 All candidates compute the same order statistic, so a choice changes speed,
 never results; the tuner still checks that every candidate's output equals the
@@ -32,6 +33,9 @@ TUNING_DIR = os.path.join(PKG, "tuning")
 WINDOWS = (3, 5, 7, 9, 11, 13, 15)
 SELECT_BY_NAME = {"network": irfilter.IRF_SELECT_NETWORK, "bisect": irfilter.IRF_SELECT_BISECT}
 NETWORK_MAX_WINDOW = 15
+FUSED_MAX_WINDOW = 9
+FUSION_CHOICES = (0, 256, 512)  # separate launches, fused with 256 or 512 threads
+FUSION_MARGIN = 1.03  # a fixed fusion choice replaces the automatic one only if this much faster
 
 
 def candidates(window: int) -> List[Tuple[int, int]]:
@@ -75,6 +79,9 @@ def apply(table: dict) -> None:
     for dt, per_window in table.get("single", {}).items():
         for k, ent in per_window.items():
             irfilter.set_tuning(dt, int(k), int(ent["threads"]), SELECT_BY_NAME[ent["select"]])
+    for dt, per_window in table.get("fusion", {}).items():
+        for k, ent in per_window.items():
+            irfilter.set_fusion(dt, int(k), int(ent["threads"]))
     if "batch" in table:
         irfilter.set_batch_threads(int(table["batch"]["threads"]))
 
@@ -180,6 +187,50 @@ def tune_single(torch, dtype: str, windows: Sequence[int] = WINDOWS, frames: int
     return out
 
 
+def tune_fusion(torch, dtype: str, windows: Sequence[int] = (3, 5, 7, 9), frames: int = 256, rounds: int = 3,
+                reps: int = 5, pool=None, log: Callable[[str], None] = lambda m: None) -> Dict[str, dict]:
+    """Fused or separate passes, per window, for two-pass ``ir_filter_run_frames``
+    on a ``frames``-frame stack of ``pool`` (default: :func:`default_frames`).
+    The library's automatic choice (by tile coverage, per frame size) is kept
+    unless a fixed choice beats it on this workload by FUSION_MARGIN."""
+    src = _stack(torch, pool or default_frames(dtype), frames)
+    dst = torch.empty_like(src)
+    ref = torch.empty_like(src)
+    scratch = torch.empty_like(src)
+    out = {}
+    for k in windows:
+        if k > FUSED_MAX_WINDOW:
+            continue
+        before = irfilter.get_fusion(dtype, k)
+        irfilter.set_fusion(dtype, k, 0)
+        irfilter.ir_filter_run_frames(src, ref, k, passes=2, scratch=scratch)
+
+        def run():
+            irfilter.ir_filter_run_frames(src, dst, k, passes=2, scratch=scratch)
+
+        for t in FUSION_CHOICES:
+            irfilter.set_fusion(dtype, k, t)
+            run()
+            torch.cuda.synchronize()
+            if not _same(torch, dst, ref):
+                irfilter.set_fusion(dtype, k, before)
+                raise RuntimeError(f"{dtype} {k}x{k}: two passes fused with {t} threads differ from separate passes")
+        best = {t: float("inf") for t in FUSION_CHOICES}
+        for _ in range(rounds):
+            for t in FUSION_CHOICES:
+                irfilter.set_fusion(dtype, k, t)
+                best[t] = min(best[t], _event_ms(torch, run, reps))
+        irfilter.set_fusion(dtype, k, irfilter.FUSION_AUTO)
+        auto = irfilter.resolve_fusion(dtype, k, int(src.shape[2]), int(src.shape[1]))
+        fastest = min(FUSION_CHOICES, key=lambda t: best[t])
+        choice = irfilter.FUSION_AUTO if best[auto] <= best[fastest] * FUSION_MARGIN else fastest
+        irfilter.set_fusion(dtype, k, choice)
+        out[str(k)] = {"threads": choice, "auto": auto, "ms": {str(t): round(v, 4) for t, v in best.items()}}
+        name = {irfilter.FUSION_AUTO: f"automatic ({auto})", 0: "separate"}.get(choice, f"fused, {choice} threads")
+        log(f"{dtype} {k}x{k} two passes: {name}  {out[str(k)]['ms']}")
+    return out
+
+
 def tune_batch(torch, n: int = 256, rounds: int = 3, reps: int = 5,
                log: Callable[[str], None] = lambda m: None) -> dict:
     """Batch workgroup size on the uneven 256-frame batch (sizes 160x120 to
@@ -237,10 +288,12 @@ def tune(torch, quick: bool = False, log: Callable[[str], None] = lambda m: None
         "single": f"{frames} frames of 640x512 per pixel type (random-valued impulses at 10/30/60% and mixed "
                   f"at 40% for u16; salt-and-pepper 20% and mixed 40% for u8), run_frames, best of {rounds} "
                   "interleaved rounds",
+        "fusion": "the same stacks, two passes (windows up to 9x9)",
         "batch": "256 uneven frames (160x120..1280x1024, u8/u16, windows 3..9, mixed impulses 5-60%)"},
-        "single": {}}
+        "single": {}, "fusion": {}}
     for dt in ("u16", "u8"):
         table["single"][dt] = tune_single(torch, dt, frames=frames, rounds=rounds, log=log)
+        table["fusion"][dt] = tune_fusion(torch, dt, frames=frames, rounds=rounds, log=log)
     table["batch"] = tune_batch(torch, rounds=rounds, log=log)
     table["seconds"] = round(time.time() - t0, 1)
     return table

@@ -160,15 +160,28 @@ __device__ __forceinline__ uint4 splat8(uint32_t v) {
 // gx, columns clamped to the frame: a vector load when the chunk lies inside
 // (and the layout is 16-byte aligned), one pixel repeated when it lies wholly
 // left or right of the frame, per-pixel clamped loads when it straddles an edge.
-template <typename T>
+// HALF: gx is 4 more than a multiple of 8, so the chunk is loaded as two halves
+// (each then aligned to its own size).
+template <typename T, bool HALF = false>
 __device__ __forceinline__ uint4 load_chunk(const uint8_t *frame, uint32_t row_off, int gx, int W,
                                             bool aligned) {
     if (aligned && gx >= 0 && gx + 8 <= W) {
         const uint32_t off = row_off + (uint32_t)gx * (uint32_t)sizeof(T);
-        if constexpr (sizeof(T) == 2)
+        if constexpr (HALF) {
+            if constexpr (sizeof(T) == 2) {
+                const uint2 lo = *reinterpret_cast<const uint2 *>(frame + off);
+                const uint2 hi = *reinterpret_cast<const uint2 *>(frame + off + 8u);
+                return make_uint4(lo.x, lo.y, hi.x, hi.y);
+            } else {
+                const uint32_t lo = *reinterpret_cast<const uint32_t *>(frame + off);
+                const uint32_t hi = *reinterpret_cast<const uint32_t *>(frame + off + 4u);
+                return widen8(make_uint2(lo, hi));
+            }
+        } else if constexpr (sizeof(T) == 2) {
             return *reinterpret_cast<const uint4 *>(frame + off);
-        else
+        } else {
             return widen8(*reinterpret_cast<const uint2 *>(frame + off));
+        }
     }
     if (gx + 8 <= 0) return splat8(load_px<T>(frame, row_off, 0));
     if (gx >= W) return splat8(load_px<T>(frame, row_off, W - 1));
@@ -185,7 +198,7 @@ __device__ __forceinline__ uint4 load_chunk(const uint8_t *frame, uint32_t row_o
 // t / 16 + NT / 16, ... and, if t < 2 * rows, the left (t even) or right halo
 // chunk of row t / 2, so a thread's column is the same on every tile.  All
 // loads are issued before the first LDS write.
-template <typename T, int K, int NT = kThreads>
+template <typename T, int K, int NT = kThreads, bool HALF = false>
 __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
                                           int y0, bool aligned, uint16_t *tile) {
     using G = Geometry<K, NT>;
@@ -203,12 +216,13 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
         const int row = row0 + j * kStep;
         if (j < kRounds - 1 || row < G::rows) {
             const int gy = min(max(ytop + row, 0), H - 1);
-            v[j] = load_chunk<T>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 + 8 * cx, W, aligned);
+            v[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 + 8 * cx, W, aligned);
         }
     }
     if (tid < 2 * G::rows) {
         const int gy = min(max(ytop + hrow, 0), H - 1);
-        h = load_chunk<T>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 - kHalo + 8 * hcol, W, aligned);
+        h = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 - kHalo + 8 * hcol, W,
+                                aligned);
     }
 #pragma unroll
     for (int j = 0; j < kRounds; ++j) {
@@ -482,6 +496,19 @@ __device__ __forceinline__ uint32_t valid_bits(int R, int W, int H, int px, int 
     if (px + 1 < W) m |= rb << 16;
     if (px + 2 < W) m |= rb << 8;
     if (px + 3 < W) m |= rb << 24;
+    return m;
+}
+
+// Bits of the thread's block (columns px..px+3, rows py..py+R-1, any of them
+// possibly negative) whose pixel lies in columns [xlo, xhi) and rows [ylo, yhi).
+__device__ __forceinline__ uint32_t box_bits(int R, int px, int py, int xlo, int xhi, int ylo, int yhi) {
+    const int r0 = min(max(ylo - py, 0), R), r1 = min(max(yhi - py, 0), R);
+    const uint32_t rb = r1 > r0 ? (((r1 - r0) >= 32 ? 0xffffffffu : ((1u << (r1 - r0)) - 1u)) << r0) : 0u;
+    uint32_t m = 0;
+    if (px + 0 >= xlo && px + 0 < xhi) m |= rb;
+    if (px + 1 >= xlo && px + 1 < xhi) m |= rb << 16;
+    if (px + 2 >= xlo && px + 2 < xhi) m |= rb << 8;
+    if (px + 3 >= xlo && px + 3 < xhi) m |= rb << 24;
     return m;
 }
 
@@ -768,6 +795,73 @@ struct TileSmem {
     uint32_t count;             // list length
 };
 
+// Steps 3 and 4 on a tile staged in LDS: the flagged pixels (bits of each
+// thread's 4 x R block whose centre, column 0 of row 0, is LDS value centre0)
+// are compacted into the list, their window medians are selected, and every
+// thread writes its own medians back into the tile.  sm.count must be 0, and
+// visible to every thread, on entry.  On return the tile holds the results at
+// the calling thread's pixels only: reading another thread's pixels needs a
+// barrier first.  `rot` rotates which wave starts the list.  Returns the
+// number of flagged pixels of the calling wave (wave-uniform).
+template <int K, int NT, int SEL>
+__device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32_t flags, int centre0,
+                                                     int rot) {
+    using G = Geometry<K, NT>;
+    static_assert(SEL == kSelectBisect || (SEL == kSelectNetwork && K <= kNetworkMaxWindow),
+                  "no selection network for this window");
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const uint32_t cnt = __builtin_popcount(flags);
+    const uint32_t incl = wave_inclusive_sum(cnt);
+    const uint32_t wave_total = __builtin_amdgcn_readlane(incl, 63);
+    // 3. compaction: one LDS atomic per wave reserves the wave's list slots;
+    //    a thread's entries are contiguous and in flag-bit order
+    uint32_t wbase = 0;
+    if (lane == 63 && wave_total != 0) wbase = atomicAdd(&sm.count, wave_total);
+    const uint32_t first = __builtin_amdgcn_readlane(wbase, 63) + incl - cnt;
+    {
+        uint32_t m = flags, j = first;
+        while (m) {
+            const int b = __builtin_ctz(m);
+            m &= m - 1;
+            sm.list[j++] = (uint16_t)(centre0 + bit_row(b) * kLdsPitch + bit_col(b));
+        }
+    }
+    __syncthreads();
+    const uint32_t total = sm.count;
+    // 4. medians, two list entries per lane, consecutive lanes first so that as
+    //    few waves as possible run the selection; which wave starts the list
+    //    rotates with `rot` (waves sit on fixed SIMDs)
+    constexpr int corner = G::r * kLdsPitch + G::r;
+    const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)rot) % NT;
+    if constexpr (SEL == kSelectBisect) {
+        // one window per lane
+        for (uint32_t i = slot; i < total; i += NT) {
+            const uint32_t e0 = sm.list[i];
+            sm.list[i] = (uint16_t)median_registers<K>(sm.tile + e0 - corner);
+        }
+    } else {
+        for (uint32_t i = 2 * slot; i < total; i += 2 * NT) {
+            const uint32_t e0 = sm.list[i];
+            const uint32_t e1 = (i + 1 < total) ? sm.list[i + 1] : e0;
+            const uint32_t med = median_pair<K>(sm.tile, e0 - corner, e1 - corner);
+            sm.list[i] = (uint16_t)(med & 0xffffu);
+            if (i + 1 < total) sm.list[i + 1] = (uint16_t)(med >> 16);
+        }
+    }
+    __syncthreads();
+    // results back into the tile at the thread's own pixels
+    {
+        uint32_t m = flags, j = first;
+        while (m) {
+            const int b = __builtin_ctz(m);
+            m &= m - 1;
+            sm.tile[centre0 + bit_row(b) * kLdsPitch + bit_col(b)] = sm.list[j++];
+        }
+    }
+    return wave_total;
+}
+
 // One tile already staged in LDS: detection, compaction of the flagged pixels,
 // selection, then the tile (flagged pixels replaced) is stored.  Returns the
 // number of flagged pixels the calling wave found (wave-uniform).
@@ -811,12 +905,8 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         flags = valid;
     }
 
-    const int lane = tid & 63;
-    const uint32_t cnt = __builtin_popcount(flags);
-    const uint32_t incl = wave_inclusive_sum(cnt);
-    const uint32_t wave_total = __builtin_amdgcn_readlane(incl, 63);
-
     if constexpr (MODE == MODE_DETECT) {
+        const uint32_t wave_total = __builtin_amdgcn_readlane(wave_inclusive_sum(__builtin_popcount(flags)), 63);
         uint8_t *m = a.mask_out + (uint64_t)f * a.mask_stride;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -834,52 +924,8 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         }
         return wave_total;
     } else {
-        // 3. compaction: one LDS atomic per wave reserves the wave's list slots;
-        //    a thread's entries are contiguous and in flag-bit order
-        uint32_t wbase = 0;
-        if (lane == 63 && wave_total != 0) wbase = atomicAdd(&sm.count, wave_total);
-        const uint32_t first = __builtin_amdgcn_readlane(wbase, 63) + incl - cnt;
         const int centre0 = (strip * R + G::r) * kLdsPitch + kHalo + 4 * tx;
-        {
-            uint32_t m = flags, j = first;
-            while (m) {
-                const int b = __builtin_ctz(m);
-                m &= m - 1;
-                sm.list[j++] = (uint16_t)(centre0 + bit_row(b) * kLdsPitch + bit_col(b));
-            }
-        }
-        __syncthreads();
-        const uint32_t total = sm.count;
-        // 4. medians, two list entries per lane, consecutive lanes first so
-        //    that as few waves as possible run the selection; which wave starts
-        //    the list rotates with the tile (waves sit on fixed SIMDs)
-        constexpr int corner = G::r * kLdsPitch + G::r;
-        const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)tile) % NT;
-        if constexpr (SEL == kSelectBisect) {
-            // one window per lane
-            for (uint32_t i = slot; i < total; i += NT) {
-                const uint32_t e0 = sm.list[i];
-                sm.list[i] = (uint16_t)median_registers<K>(sm.tile + e0 - corner);
-            }
-        } else {
-            for (uint32_t i = 2 * slot; i < total; i += 2 * NT) {
-                const uint32_t e0 = sm.list[i];
-                const uint32_t e1 = (i + 1 < total) ? sm.list[i + 1] : e0;
-                const uint32_t med = median_pair<K>(sm.tile, e0 - corner, e1 - corner);
-                sm.list[i] = (uint16_t)(med & 0xffffu);
-                if (i + 1 < total) sm.list[i + 1] = (uint16_t)(med >> 16);
-            }
-        }
-        __syncthreads();
-        // results back into the tile at the thread's own pixels
-        {
-            uint32_t m = flags, j = first;
-            while (m) {
-                const int b = __builtin_ctz(m);
-                m &= m - 1;
-                sm.tile[centre0 + bit_row(b) * kLdsPitch + bit_col(b)] = sm.list[j++];
-            }
-        }
+        const uint32_t wave_total = median_into_tile<K, NT, SEL>(sm, flags, centre0, tile);
         // 5. store the thread's block (its own LDS values only: no barrier needed)
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
         const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform

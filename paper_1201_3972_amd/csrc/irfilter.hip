@@ -26,7 +26,18 @@ constexpr int kVersion = (1 << 16) | 0;
 // through ir_filter_set_tuning; a launch reads its entry once.
 std::atomic<uint32_t> g_tuning[2][8];
 
+// Fusion of pass pairs, per pixel type and window: 0 means automatic (the
+// default), 1 runs every pass as its own launch, otherwise the fused kernel's
+// workgroup size.
+std::atomic<uint32_t> g_fusion[2][8];
+
 int window_slot(int window) { return (window - 3) / 2; }
+
+int fusion_of(irf_dtype dtype, int window) {
+    const uint32_t v = g_fusion[dtype == IRF_U8 ? 0 : 1][window_slot(window)].load(std::memory_order_relaxed);
+    if (v == 0) return kFusionAuto;
+    return v == 1 ? 0 : (int)v;
+}
 
 Tuning tuning_of(irf_dtype dtype, int window) {
     const uint32_t v = g_tuning[dtype == IRF_U8 ? 0 : 1][window_slot(window)].load(std::memory_order_relaxed);
@@ -52,6 +63,31 @@ irf_status launch(irf_dtype dtype, int window, int nframes, StackArgs a, hipStre
     const bool ok = dtype == IRF_U8 ? launch_stack_u8(window, MODE, t, a, s)
                                     : launch_stack_u16(window, MODE, t, a, s);
     if (!ok) return IRF_ERR_WINDOW;
+    if (hipGetLastError() != hipSuccess) return IRF_ERR_HIP;
+    return IRF_OK;
+}
+
+// Fused workgroup size for pairs of passes over width x height frames, 0 for
+// separate passes.
+int resolved_fusion(irf_dtype dtype, int window, int width, int height) {
+    const int f = fusion_of(dtype, window);
+    return f == kFusionAuto ? auto_fusion(width, height, window, tuning_of(dtype, window).threads) : f;
+}
+
+// Two passes of the filter in one launch; a.count (if set) receives both
+// passes' counts, in two consecutive entries.
+irf_status launch_fused(irf_dtype dtype, int window, int threads, int nframes, StackArgs a, hipStream_t s) {
+    const int oh = fused_tile_rows(window, threads);
+    a.tiles_x = (a.width + kFusedTileW - 1) / kFusedTileW;
+    const int tiles_y = (a.height + oh - 1) / oh;
+    const uint64_t per_frame = (uint64_t)a.tiles_x * (uint64_t)tiles_y;
+    const uint64_t total = per_frame * (uint64_t)nframes;
+    if (total > 0x7fffffffull) return IRF_ERR_DIMS;
+    a.tiles_per_frame = (int)per_frame;
+    a.total_tiles = (int)total;
+    a.pk_one = 0x00010001u;
+    (void)hipGetLastError();
+    if (!launch_fused2(bytes_of(dtype), window, threads, a, s)) return IRF_ERR_WINDOW;
     if (hipGetLastError() != hipSuccess) return IRF_ERR_HIP;
     return IRF_OK;
 }
@@ -90,12 +126,17 @@ irf_status run_frames(const void *src, size_t src_pitch, size_t src_stride, void
         if (overlap(cs, ss) || overlap(cs, ds)) return IRF_ERR_ALIAS;
     }
     if ((st = zero_counts(counts, passes, stream))) return st;
-    // Pass i reads A_{i-1} and writes A_i; A_0 = src, A_passes = dst, and the
-    // intermediate frames alternate so that an even distance from the end is dst.
+    // Pairs of passes run fused where a fused kernel is enabled, an odd last
+    // pass on its own.  Launch l reads the frame launch l-1 wrote (src for the
+    // first) and writes dst when an even number of launches follow it, else
+    // scratch, so no launch reads the frame it writes.
+    const int fuse = passes >= 2 ? resolved_fusion(dtype, window, width, height) : 0;
+    const int launches = fuse ? (passes + 1) / 2 : passes;
     const void *in = src;
     size_t in_pitch = src_pitch, in_stride = src_stride;
-    for (int p = 1; p <= passes; ++p) {
-        const bool to_dst = ((passes - p) & 1) == 0;
+    for (int l = 1, p = 1; l <= launches; ++l) {
+        const int np = (fuse && p < passes) ? 2 : 1;  // passes in this launch, p being the first
+        const bool to_dst = ((launches - l) & 1) == 0;
         void *out = to_dst ? dst : scratch;
         const size_t out_pitch = to_dst ? dst_pitch : scratch_pitch;
         const size_t out_stride = to_dst ? dst_stride : scratch_stride;
@@ -111,7 +152,10 @@ irf_status run_frames(const void *src, size_t src_pitch, size_t src_stride, void
         a.aligned = is16(in) && is16(out) && is16(in_pitch) && is16(out_pitch) &&
                     (nframes == 1 || (is16(in_stride) && is16(out_stride)));
         a.count = counts ? reinterpret_cast<unsigned long long *>(counts + (p - 1)) : nullptr;
-        if ((st = launch<MODE_FNR>(dtype, window, nframes, a, stream))) return st;
+        st = np == 2 ? launch_fused(dtype, window, fuse, nframes, a, stream)
+                     : launch<MODE_FNR>(dtype, window, nframes, a, stream);
+        if (st) return st;
+        p += np;
         in = out;
         in_pitch = out_pitch;
         in_stride = out_stride;
@@ -245,6 +289,38 @@ irf_status ir_filter_get_tuning(irf_dtype dtype, int window, int *threads, int *
     const Tuning t = tuning_of(dtype, window);
     *threads = t.threads;
     *select = t.select;
+    return IRF_OK;
+}
+
+irf_status ir_filter_get_fusion(irf_dtype dtype, int window, int *threads) {
+    if (!threads) return IRF_ERR_NULL;
+    if (dtype != IRF_U8 && dtype != IRF_U16) return IRF_ERR_DTYPE;
+    if (window < 3 || window > IRF_MAX_WINDOW || (window & 1) == 0) return IRF_ERR_WINDOW;
+    *threads = fusion_of(dtype, window);
+    return IRF_OK;
+}
+
+irf_status ir_filter_resolve_fusion(irf_dtype dtype, int window, int width, int height, int *threads) {
+    if (!threads) return IRF_ERR_NULL;
+    const irf_status st = check_common(width, height, 1, dtype, window);
+    if (st) return st;
+    *threads = resolved_fusion(dtype, window, width, height);
+    return IRF_OK;
+}
+
+irf_status ir_filter_set_fusion(irf_dtype dtype, int window, int threads) {
+    if (dtype != IRF_U8 && dtype != IRF_U16) return IRF_ERR_DTYPE;
+    if (window < 3 || window > IRF_MAX_WINDOW || (window & 1) == 0) return IRF_ERR_WINDOW;
+    uint32_t v;
+    if (threads == -1)
+        v = 0;
+    else if (threads == 0)
+        v = 1;
+    else if (fused_available(window, threads))
+        v = (uint32_t)threads;
+    else
+        return IRF_ERR_TUNING;
+    g_fusion[dtype == IRF_U8 ? 0 : 1][window_slot(window)].store(v, std::memory_order_relaxed);
     return IRF_OK;
 }
 

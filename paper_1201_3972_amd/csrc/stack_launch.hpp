@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fnr_device.hpp"
+#include "fused_device.hpp"
 #include "host_common.hpp"
 
 namespace irf {
@@ -32,6 +33,44 @@ inline bool tuning_available(int window, Tuning t) {
 // the combination has no kernel (nothing is launched then).
 bool launch_stack_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
 bool launch_stack_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
+
+// Two passes in one launch (fused.hip): windows up to 9x9, workgroups of 256 or
+// 512 threads (blocks of 128 x 64 or 128 x 128 pixels).
+inline bool fused_available(int window, int threads) {
+    return window >= 3 && window <= kFusedMaxWindow && (window & 1) && (threads == 256 || threads == 512);
+}
+// Pass-2 output rows of a fused tile.
+inline int fused_tile_rows(int window, int threads) {
+    return threads / kThreadsX * Geometry<3>::R - 2 * (window / 2);
+}
+// Fusion setting that picks per frame size (the untuned default).
+constexpr int kFusionAuto = -1;
+// The automatic choice for a W x H frame whose single passes run with
+// plain_threads: the fused workgroup size whose tiles cover the fewest pixels,
+// if they cover no more than the plain tiles of two separate passes, else 0.
+// Both kernels are bound by vector ALU work per covered pixel, so fusion only
+// pays where its overlapping tiles cost no extra work (6 fused tiles of 120
+// output columns cover a 640-pixel row that 5 plain tiles cover, for one).
+inline int auto_fusion(int width, int height, int window, int plain_threads) {
+    if (window > kFusedMaxWindow) return 0;
+    auto cdiv = [](long long a, long long b) { return (a + b - 1) / b; };
+    const long long ph = plain_threads / kThreadsX * Geometry<3>::R;
+    const long long plain = 2 * cdiv(width, kTileW) * cdiv(height, ph) * kTileW * ph;
+    int best = 0;
+    long long best_px = plain;
+    for (int t : {256, 512}) {
+        const long long th = t / kThreadsX * Geometry<3>::R;
+        const long long px = 2 * cdiv(width, kFusedTileW) * cdiv(height, fused_tile_rows(window, t)) * kTileW * th;
+        if (px <= best_px && (best == 0 || px < best_px)) {
+            best = t;
+            best_px = px;
+        }
+    }
+    return best;
+}
+// Launch the fused kernel for a.total_tiles fused tiles (the caller sets the
+// tile counts from kFusedTileW and fused_tile_rows); false if no kernel exists.
+bool launch_fused2(int bytes, int window, int threads, const StackArgs &a, hipStream_t s);
 
 namespace stack_impl {
 

@@ -46,6 +46,9 @@ SIGNATURES = {
     "ir_filter_version": (_i32, []),
     "ir_filter_get_tuning": (_i32, [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "ir_filter_set_tuning": (_i32, [_i32, _i32, _i32, _i32]),
+    "ir_filter_get_fusion": (_i32, [_i32, _i32, ctypes.POINTER(_i32)]),
+    "ir_filter_set_fusion": (_i32, [_i32, _i32, _i32]),
+    "ir_filter_resolve_fusion": (_i32, [_i32, _i32, _i32, _i32, ctypes.POINTER(_i32)]),
     "ir_filter_set_batch_threads": (_i32, [_i32]),
     "ir_filter_get_batch_threads": (_i32, []),
     "ir_filter_plan_frame_tiles": (_i32, [_vp, _i32, _i32]),
@@ -245,6 +248,32 @@ def get_tuning(dtype, window: int):
 def set_tuning(dtype, window: int, threads: int, select: int) -> None:
     """Set (threads, select) for a pixel type and window; (0, 0) restores the default."""
     _check("ir_filter_set_tuning", load().ir_filter_set_tuning(_dtype_arg(dtype), window, threads, select))
+
+
+FUSION_AUTO = -1
+
+
+def get_fusion(dtype, window: int) -> int:
+    """Fusion setting of (dtype, window): the fused kernel's workgroup size,
+    0 for separate launches, or FUSION_AUTO (chosen per frame size)."""
+    t = ctypes.c_int()
+    _check("ir_filter_get_fusion", load().ir_filter_get_fusion(_dtype_arg(dtype), window, ctypes.byref(t)))
+    return t.value
+
+
+def resolve_fusion(dtype, window: int, width: int, height: int) -> int:
+    """What a run of two or more passes over width x height frames uses: the
+    fused workgroup size, or 0 for separate passes."""
+    t = ctypes.c_int()
+    _check("ir_filter_resolve_fusion", load().ir_filter_resolve_fusion(_dtype_arg(dtype), window, width, height,
+                                                                       ctypes.byref(t)))
+    return t.value
+
+
+def set_fusion(dtype, window: int, threads: int) -> None:
+    """Fuse pairs of passes with workgroups of `threads` (256 or 512), run
+    passes separately (0), or choose per frame size (FUSION_AUTO, the default)."""
+    _check("ir_filter_set_fusion", load().ir_filter_set_fusion(_dtype_arg(dtype), window, threads))
 
 
 def set_batch_threads(threads: int) -> None:

@@ -138,5 +138,13 @@ def test_autotuner_short_run(dev):
         assert (ent["threads"], autotune.SELECT_BY_NAME[ent["select"]]) in autotune.candidates(int(k))
         assert irfilter.get_tuning("u16", int(k)) == (ent["threads"], autotune.SELECT_BY_NAME[ent["select"]])
         assert len(ent["ms"]) == len(autotune.candidates(int(k)))
+    fu = autotune.tune_fusion(torch, "u16", windows=(3, 9, 11), frames=4, rounds=1, reps=1, pool=pool)
+    assert set(fu) == {"3", "9"}  # no fused kernel above 9x9
+    for k, ent in fu.items():
+        assert ent["threads"] in autotune.FUSION_CHOICES + (irfilter.FUSION_AUTO,)
+        assert irfilter.get_fusion("u16", int(k)) == ent["threads"]
+        if ent["threads"] == irfilter.FUSION_AUTO:
+            assert ent["auto"] == irfilter.resolve_fusion("u16", int(k), 256, 96)
+        irfilter.set_fusion("u16", int(k), -1)
     b = autotune.tune_batch(torch, n=12, rounds=1, reps=1)
     assert b["threads"] in (128, 256) and irfilter.get_batch_threads() == b["threads"]

@@ -26,6 +26,7 @@ def _restore_defaults():
     for dt in ("u8", "u16"):
         for k in range(3, 16, 2):
             irfilter.set_tuning(dt, k, 0, 0)
+            irfilter.set_fusion(dt, k, -1)
     irfilter.set_batch_threads(0)
 
 
@@ -60,6 +61,82 @@ def test_invalid_tuning(args, status):
     assert lib.ir_filter_set_tuning(3, 5, 128, 1) == -4
 
 
+def test_fusion_set_get_and_restore():
+    for dt in ("u8", "u16"):
+        for k in range(3, 16, 2):
+            assert irfilter.get_fusion(dt, k) == irfilter.FUSION_AUTO
+    irfilter.set_fusion("u16", 5, 256)
+    assert irfilter.get_fusion("u16", 5) == 256
+    irfilter.set_fusion("u16", 5, 0)
+    assert irfilter.get_fusion("u16", 5) == 0
+    u16_9 = irfilter.get_fusion("u16", 9)
+    irfilter.set_fusion("u8", 9, 512 if u16_9 != 512 else 256)
+    assert irfilter.get_fusion("u8", 9) != u16_9
+    assert irfilter.get_fusion("u16", 9) == u16_9  # per pixel type
+    irfilter.set_fusion("u16", 5, -1)
+    irfilter.set_fusion("u8", 9, -1)
+    assert irfilter.get_fusion("u16", 5) == irfilter.get_fusion("u8", 9) == irfilter.FUSION_AUTO
+    irfilter.set_fusion("u16", 11, 0)  # separate passes are always available
+    assert irfilter.get_fusion("u16", 11) == 0
+
+
+def _covered(W, H, k, fused_threads, plain_threads):
+    """Pixels two passes cover: plain 128 x TH tiles twice, or fused blocks of
+    128 x TH whose outputs are 120 x (TH - k + 1)."""
+    cdiv = lambda a, b: -(-a // b)
+    if fused_threads == 0:
+        th = plain_threads // 4
+        return 2 * cdiv(W, 128) * cdiv(H, th) * 128 * th
+    th = fused_threads // 4
+    return 2 * cdiv(W, 120) * cdiv(H, th - k + 1) * 128 * th
+
+
+@pytest.mark.parametrize("dt,k,W,H", [
+    ("u8", 3, 320, 240), ("u8", 5, 320, 240), ("u16", 5, 640, 512), ("u16", 7, 640, 512),
+    ("u16", 5, 1920, 1080), ("u8", 3, 364, 244), ("u16", 9, 100, 60), ("u8", 11, 320, 240),
+    ("u16", 3, 1, 1), ("u8", 7, 4000, 3000)])
+def test_automatic_fusion_covers_no_more_pixels(dt, k, W, H):
+    plain = irfilter.get_tuning(dt, k)[0]
+    got = irfilter.resolve_fusion(dt, k, W, H)
+    if k > 9:
+        assert got == 0
+        return
+    base = _covered(W, H, k, 0, plain)
+    options = {t: _covered(W, H, k, t, plain) for t in (256, 512)}
+    best = min(options.values())
+    if best > base:
+        assert got == 0
+    else:
+        assert got in options and options[got] == best
+        assert got == 256 or options[256] > best  # ties go to the smaller workgroup
+
+
+def test_resolve_fusion_follows_the_setting():
+    assert irfilter.resolve_fusion("u8", 3, 320, 240) == 256  # equal coverage: fused
+    assert irfilter.resolve_fusion("u16", 5, 640, 512) == 0   # 6 fused tiles across vs 5 plain
+    irfilter.set_fusion("u16", 5, 512)
+    assert irfilter.resolve_fusion("u16", 5, 640, 512) == 512
+    irfilter.set_fusion("u8", 3, 0)
+    assert irfilter.resolve_fusion("u8", 3, 320, 240) == 0
+    lib = irfilter.load()
+    assert lib.ir_filter_resolve_fusion(2, 5, 0, 10, None) == -1
+    import ctypes
+    t = ctypes.c_int()
+    assert lib.ir_filter_resolve_fusion(2, 5, 0, 10, ctypes.byref(t)) == -2
+    assert lib.ir_filter_resolve_fusion(2, 6, 10, 10, ctypes.byref(t)) == -5
+
+
+@pytest.mark.parametrize("dt,k,threads,status", [
+    ("u16", 11, 256, -11), ("u16", 15, 512, -11), ("u16", 5, 128, -11), ("u16", 5, 1, -11),
+    ("u16", 5, -2, -11), ("u16", 4, 256, -5), ("u16", 17, 0, -5),
+])
+def test_invalid_fusion(dt, k, threads, status):
+    lib = irfilter.load()
+    assert lib.ir_filter_set_fusion(irfilter._dtype_arg(dt), k, threads) == status
+    assert lib.ir_filter_set_fusion(3, 5, 256) == -4
+    assert lib.ir_filter_get_fusion(2, 5, None) == -1
+
+
 def test_get_tuning_checks_pointers():
     assert irfilter.load().ir_filter_get_tuning(2, 5, None, None) == -1
 
@@ -80,6 +157,7 @@ def test_cache_round_trip_and_apply(tmp_path):
         "key": {"arch": "gfx950", "rocm": "test"},
         "single": {"u16": {"5": {"threads": 256, "select": "bisect", "ms": {}},
                            "7": {"threads": 128, "select": "network", "ms": {}}}},
+        "fusion": {"u8": {"5": {"threads": 512, "ms": {}}}},
         "batch": {"threads": 256, "ms": {}},
     }
     path = tmp_path / "t.json"
@@ -89,6 +167,7 @@ def test_cache_round_trip_and_apply(tmp_path):
     autotune.apply(back)
     assert irfilter.get_tuning("u16", 5) == (256, irfilter.IRF_SELECT_BISECT)
     assert irfilter.get_tuning("u16", 7) == (128, irfilter.IRF_SELECT_NETWORK)
+    assert irfilter.get_fusion("u8", 5) == 512 and irfilter.get_fusion("u16", 5) == irfilter.FUSION_AUTO
     assert irfilter.get_batch_threads() == 256
 
 

@@ -60,7 +60,8 @@ typedef enum {
     IRF_ERR_PITCH = -3,   /* a pitch is smaller than one row or not below 2^24, a frame spans
                              4 GiB or more, or a stride is smaller than one frame */
     IRF_ERR_DTYPE = -4,   /* pixel type is not IRF_U8 or IRF_U16 */
-    IRF_ERR_WINDOW = -5,  /* window is not odd or outside 3..IRF_MAX_WINDOW */
+    IRF_ERR_WINDOW = -5,  /* window is not odd or outside 3..IRF_MAX_WINDOW (3..IRF_MAX_BATCH_WINDOW
+                             for batches and the server) */
     IRF_ERR_PASSES = -6,  /* passes outside 1..IRF_MAX_PASSES, or scratch missing for passes >= 2 */
     IRF_ERR_ALIAS = -7,   /* an output overlaps an input or another output */
     IRF_ERR_HIP = -8,     /* a HIP call failed (the HIP error is cleared) */
@@ -70,7 +71,10 @@ typedef enum {
 } irf_status;
 
 #define IRF_MAX_DIM 32768
-#define IRF_MAX_WINDOW 15
+/* Single-size entry points take windows up to 31x31; batch plans and the
+ * server up to 15x15. */
+#define IRF_MAX_WINDOW 31
+#define IRF_MAX_BATCH_WINDOW 15
 #define IRF_MAX_PASSES 16
 
 /*
@@ -273,13 +277,17 @@ void ir_filter_server_destroy(irf_server *server);
  * per pixel type and window, the workgroup size (128 threads on tiles of
  * 128x32 pixels, or 256 threads on 128x64) and the selection algorithm:
  *   IRF_SELECT_NETWORK  forgetful selection networks, two windows per lane
- *   IRF_SELECT_BISECT   grey-level bisection, one window per lane (any window)
- * Untuned defaults: 128 threads except 256 for 7x7, networks for every window.
+ *                       (windows up to 15x15)
+ *   IRF_SELECT_BISECT   grey-level bisection, one window per lane (up to 15x15)
+ *   IRF_SELECT_GROUP    grey-level bisection, one window per group of 8 or 16
+ *                       lanes (the only choice above 15x15)
+ * Untuned defaults: 256 threads for 7x7 and above 15x15, else 128; networks
+ * up to 15x15, group bisection above.
  * ir_filter_set_tuning(dtype, window, 0, 0)
  * restores the default; an unavailable combination returns IRF_ERR_TUNING.
  * The autotuner of the Python package measures the choices and sets them.
  */
-typedef enum { IRF_SELECT_NETWORK = 1, IRF_SELECT_BISECT = 2 } irf_select;
+typedef enum { IRF_SELECT_NETWORK = 1, IRF_SELECT_BISECT = 2, IRF_SELECT_GROUP = 3 } irf_select;
 
 irf_status ir_filter_get_tuning(irf_dtype dtype, int window, int *threads, int *select);
 irf_status ir_filter_set_tuning(irf_dtype dtype, int window, int threads, int select);

@@ -31,7 +31,8 @@ from . import irfilter
 PKG = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(PKG, "tuning")
 WINDOWS = (3, 5, 7, 9, 11, 13, 15)
-SELECT_BY_NAME = {"network": irfilter.IRF_SELECT_NETWORK, "bisect": irfilter.IRF_SELECT_BISECT}
+LARGE_WINDOWS = (17, 19, 21, 23, 25, 27, 29, 31)  # group bisection only: workgroup size is the choice
+SELECT_BY_NAME = {name: code for code, name in irfilter.SELECT_NAMES.items()}
 NETWORK_MAX_WINDOW = 15
 FUSED_MAX_WINDOW = 9
 FUSION_CHOICES = (0, 256, 512)  # separate launches, fused with 256 or 512 threads
@@ -39,10 +40,12 @@ FUSION_MARGIN = 1.03  # a fixed fusion choice replaces the automatic one only if
 
 
 def candidates(window: int) -> List[Tuple[int, int]]:
-    """Every (threads, select) with a kernel for this window."""
-    sels = [irfilter.IRF_SELECT_BISECT]
+    """Every (threads, select) with a kernel for this window: networks and
+    one-lane bisection up to 15x15, group bisection above."""
     if window <= NETWORK_MAX_WINDOW:
-        sels.insert(0, irfilter.IRF_SELECT_NETWORK)
+        sels = [irfilter.IRF_SELECT_NETWORK, irfilter.IRF_SELECT_BISECT]
+    else:
+        sels = [irfilter.IRF_SELECT_GROUP]
     return [(t, s) for t in (128, 256) for s in sels]
 
 
@@ -288,11 +291,14 @@ def tune(torch, quick: bool = False, log: Callable[[str], None] = lambda m: None
         "single": f"{frames} frames of 640x512 per pixel type (random-valued impulses at 10/30/60% and mixed "
                   f"at 40% for u16; salt-and-pepper 20% and mixed 40% for u8), run_frames, best of {rounds} "
                   "interleaved rounds",
+        "large": f"windows 17..31: {frames // 32} frames of the same stacks, best of 2 rounds",
         "fusion": "the same stacks, two passes (windows up to 9x9)",
         "batch": "256 uneven frames (160x120..1280x1024, u8/u16, windows 3..9, mixed impulses 5-60%)"},
         "single": {}, "fusion": {}}
     for dt in ("u16", "u8"):
         table["single"][dt] = tune_single(torch, dt, frames=frames, rounds=rounds, log=log)
+        table["single"][dt].update(tune_single(torch, dt, windows=LARGE_WINDOWS, frames=frames // 32,
+                                               rounds=2, reps=2, log=log))
         table["fusion"][dt] = tune_fusion(torch, dt, frames=frames, rounds=rounds, log=log)
     table["batch"] = tune_batch(torch, rounds=rounds, log=log)
     table["seconds"] = round(time.time() - t0, 1)

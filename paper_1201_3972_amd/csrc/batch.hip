@@ -240,7 +240,7 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         for (int i = 0; i < n; ++i) {
             const irf_frame &f = frames[i];
             if (!f.src || !f.dst) return IRF_ERR_NULL;
-            irf_status st = check_common(f.width, f.height, 1, f.dtype, f.window);
+            irf_status st = check_batch_frame(f.width, f.height, f.dtype, f.window);
             if (st) return st;
             const int b = bytes_of(f.dtype);
             if ((st = check_layout(f.src_pitch, 0, f.width, f.height, 1, b))) return st;

@@ -46,24 +46,21 @@ constexpr int kTileW = 128;                  // output columns per tile
 constexpr int kThreadsX = kTileW / 4;        // 32 threads across, 4 columns each
 constexpr int kStrips = kThreads / kThreadsX;  // 4 strips of R rows
 // Selection algorithm: forgetful selection networks on two windows per lane,
-// or grey-level bisection on one window per lane.
-enum Select : int { kSelectNetwork = 1, kSelectBisect = 2 };
+// grey-level bisection on one window per lane, or grey-level bisection on one
+// window per group of 8 or 16 lanes (the windows above 15x15, whose values no
+// longer fit one lane's registers).
+enum Select : int { kSelectNetwork = 1, kSelectBisect = 2, kSelectGroup = 3 };
 constexpr int kNetworkMaxWindow = 15;
 // Untuned choices of the stack kernels: 7x7 takes 256-thread workgroups on tiles
 // of twice the height, which fill its selection waves better (a 128x32 tile
 // holds about 80 window pairs at the usual impulse rates, just over one wave's
-// worth); the other windows run faster with the smaller tile.  Networks beat
+// worth); the other windows up to 15x15 run faster with the smaller tile, those
+// above (group bisection) with the larger one.  Networks beat
 // bisection at every window (by 2.4x at 15x15).  The host's tuning table starts
 // from these and an autotuner may replace them.
-constexpr int default_threads(int K) { return K == 7 ? 256 : 128; }
-constexpr int default_select(int K) { return K <= kNetworkMaxWindow ? kSelectNetwork : kSelectBisect; }
-constexpr int kHalo = 8;                     // LDS columns kept left and right of the tile
-constexpr int kLdsW = kTileW + 2 * kHalo;    // 144 16-bit values staged per LDS row
-constexpr int kChunks = kLdsW / 8;           // 8-pixel load chunks per LDS row
-// LDS row pitch in 16-bit values: 76 dwords, so rows 8 apart (the two 32-lane
-// halves of a wave during detection) fall on opposite halves of the 64 banks.
-constexpr int kLdsPitch = kLdsW + 8;
-constexpr int kMaxWindow = 15;
+constexpr int default_threads(int K) { return (K == 7 || K > kNetworkMaxWindow) ? 256 : 128; }
+constexpr int default_select(int K) { return K <= kNetworkMaxWindow ? kSelectNetwork : kSelectGroup; }
+constexpr int kMaxWindow = 31;
 
 enum Mode : int {
     MODE_DETECT = 0,       // write the noise mask (and count)
@@ -97,9 +94,18 @@ struct Geometry {
     static constexpr int TH = NT / kThreadsX * R;
     static constexpr int rows = TH + 2 * r;  // LDS rows
     static constexpr int tile_px = kTileW * TH;
-    static_assert(K >= 3 && K <= kMaxWindow && (K & 1), "odd window 3..15");
+    // LDS columns staged left and right of the tile (8 up to 17x17, 16 above),
+    // 8-pixel load chunks per LDS row, and the LDS row pitch in 16-bit values:
+    // 8 values of padding make it 76 (84) dwords, so rows 8 apart (the two
+    // 32-lane halves of a wave during detection) fall on opposite halves of the
+    // 64 banks.
+    static constexpr int halo = r <= 8 ? 8 : 16;
+    static constexpr int chunks = (kTileW + 2 * halo) / 8;
+    static constexpr int pitch = kTileW + 2 * halo + 8;
+    static_assert(K >= 3 && K <= kMaxWindow && (K & 1), "odd window 3..31");
     static_assert(NT % 64 == 0 && NT % kThreadsX == 0, "whole waves of whole thread rows");
-    static_assert(r <= kHalo, "halo must cover the window radius");
+    static_assert(r <= halo, "halo must cover the window radius");
+    static_assert(rows * pitch <= 65536, "LDS offsets are 16-bit");
 };
 
 // ---------------------------------------------------------------------------
@@ -191,26 +197,28 @@ __device__ __forceinline__ uint4 load_chunk(const uint8_t *frame, uint32_t row_o
     return make_uint4(e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16));
 }
 
-// Stage rows y0-r .. y0+TH+r-1 and columns x0-kHalo .. x0+kTileW+kHalo-1 of a
-// frame in LDS (row-major, kLdsPitch values apart), coordinates outside the
+// Stage rows y0-r .. y0+TH+r-1 and columns x0-halo .. x0+kTileW+halo-1 of a
+// frame in LDS (row-major, G::pitch values apart), coordinates outside the
 // frame clamped to the nearest edge pixel.  Each row is 16 interior chunks and
-// two halo chunks: thread t loads interior chunk t % 16 of rows t / 16,
-// t / 16 + NT / 16, ... and, if t < 2 * rows, the left (t even) or right halo
-// chunk of row t / 2, so a thread's column is the same on every tile.  All
-// loads are issued before the first LDS write.
+// 2 * HC halo chunks (HC = halo / 8 on each side): thread t loads interior
+// chunk t % 16 of rows t / 16, t / 16 + NT / 16, ... and halo chunks t,
+// t + NT, ... (chunk h is number h % (2 HC) of row h / (2 HC), the left ones
+// first), so a thread's column is the same on every tile.  All loads are
+// issued before the first LDS write.
 template <typename T, int K, int NT = kThreads, bool HALF = false>
 __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
                                           int y0, bool aligned, uint16_t *tile) {
     using G = Geometry<K, NT>;
     constexpr int kStep = NT / 16;
     constexpr int kRounds = (G::rows + kStep - 1) / kStep;
-    static_assert(kTileW == 16 * 8 && kChunks == 18, "16 interior and 2 halo chunks per row");
-    static_assert(2 * G::rows <= NT, "at most one halo chunk per thread");
+    constexpr int HC = G::halo / 8;                    // halo chunks on each side
+    constexpr int kHalos = 2 * HC * G::rows;           // halo chunks of the tile
+    constexpr int kHRounds = (kHalos + NT - 1) / NT;
+    static_assert(kTileW == 16 * 8 && G::chunks == 16 + 2 * HC, "16 interior chunks per row");
     const int tid = threadIdx.x;
     const int cx = tid & 15, row0 = tid >> 4;
-    const int hrow = tid >> 1, hcol = (tid & 1) ? kChunks - 1 : 0;
     const int ytop = y0 - G::r;
-    uint4 v[kRounds], h;
+    uint4 v[kRounds], h[kHRounds];
 #pragma unroll
     for (int j = 0; j < kRounds; ++j) {
         const int row = row0 + j * kStep;
@@ -219,18 +227,32 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
             v[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 + 8 * cx, W, aligned);
         }
     }
-    if (tid < 2 * G::rows) {
-        const int gy = min(max(ytop + hrow, 0), H - 1);
-        h = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 - kHalo + 8 * hcol, W,
-                                aligned);
+#pragma unroll
+    for (int j = 0; j < kHRounds; ++j) {
+        const int hc = tid + j * NT;
+        if (hc < kHalos) {
+            const int hrow = hc / (2 * HC), which = hc % (2 * HC);
+            const int hcol = HC == 1 ? ((hc & 1) ? G::chunks - 1 : 0) : (which < HC ? which : 16 + which);
+            const int gy = min(max(ytop + hrow, 0), H - 1);
+            h[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 - G::halo + 8 * hcol,
+                                       W, aligned);
+        }
     }
 #pragma unroll
     for (int j = 0; j < kRounds; ++j) {
         const int row = row0 + j * kStep;
         if (j < kRounds - 1 || row < G::rows)
-            *reinterpret_cast<uint4 *>(tile + row * kLdsPitch + 8 * (cx + 1)) = v[j];
+            *reinterpret_cast<uint4 *>(tile + row * G::pitch + 8 * (cx + HC)) = v[j];
     }
-    if (tid < 2 * G::rows) *reinterpret_cast<uint4 *>(tile + hrow * kLdsPitch + 8 * hcol) = h;
+#pragma unroll
+    for (int j = 0; j < kHRounds; ++j) {
+        const int hc = tid + j * NT;
+        if (hc < kHalos) {
+            const int hrow = hc / (2 * HC), which = hc % (2 * HC);
+            const int hcol = HC == 1 ? ((hc & 1) ? G::chunks - 1 : 0) : (which < HC ? which : 16 + which);
+            *reinterpret_cast<uint4 *>(tile + hrow * G::pitch + 8 * hcol) = h[j];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -360,7 +382,7 @@ __device__ __forceinline__ uint32_t detect_block_blocks(const uint16_t *tile, in
                                                         uint32_t pk_one) {
     using G = Geometry<K>;
     constexpr int R = G::R, L = R + K - 1;
-    const uint16_t *base = tile + strip * R * kLdsPitch + kHalo + 4 * tx;
+    const uint16_t *base = tile + strip * R * G::pitch + G::halo + 4 * tx;
     uint32_t mn0[L], mn1[L], mx0[L], mx1[L];  // horizontal results, then block suffixes
     uint32_t pmn0[L], pmn1[L], pmx0[L], pmx1[L];  // running prefixes within a block
     uint32_t c0[R], c1[R];
@@ -378,7 +400,7 @@ __device__ __forceinline__ uint32_t detect_block_blocks(const uint16_t *tile, in
         constexpr int i = decltype(ic)::value;
         constexpr int blk = i / K, first = blk * K;
         uint32_t a, b;
-        row_minmax<G::r>(base + i * kLdsPitch, mn0[i], mn1[i], mx0[i], mx1[i], a, b);
+        row_minmax<G::r>(base + i * G::pitch, mn0[i], mn1[i], mx0[i], mx1[i], a, b);
         if constexpr (i >= G::r && i < G::r + R) {
             c0[i - G::r] = a;
             c1[i - G::r] = b;
@@ -419,7 +441,7 @@ __device__ __forceinline__ uint32_t detect_block_core(const uint16_t *tile, int 
     using G = Geometry<K>;
     constexpr int R = G::R, L = R + K - 1, A = R - 1;
     static_assert(K > R && A > 0, "core split needs windows taller than the block");
-    const uint16_t *base = tile + strip * R * kLdsPitch + kHalo + 4 * tx;
+    const uint16_t *base = tile + strip * R * G::pitch + G::halo + 4 * tx;
     uint32_t mn0[A], mn1[A], mx0[A], mx1[A];          // rows before the core, then suffixes
     uint32_t cmn0 = 0, cmn1 = 0, cmx0 = 0, cmx1 = 0;  // core
     uint32_t pmn0 = 0, pmn1 = 0, pmx0 = 0, pmx1 = 0;  // prefix of the rows after the core
@@ -435,7 +457,7 @@ __device__ __forceinline__ uint32_t detect_block_core(const uint16_t *tile, int 
     static_for(std::make_integer_sequence<int, L>{}, [&](auto ic) {
         constexpr int i = decltype(ic)::value;
         uint32_t a0, a1, b0, b1, ca, cb;
-        row_minmax<G::r>(base + i * kLdsPitch, a0, a1, b0, b1, ca, cb);
+        row_minmax<G::r>(base + i * G::pitch, a0, a1, b0, b1, ca, cb);
         if constexpr (i >= G::r && i < G::r + R) {
             c0[i - G::r] = ca;
             c1[i - G::r] = cb;
@@ -598,8 +620,8 @@ __device__ __forceinline__ void load_pair_row(const PairRow &w, int row, uint32_
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             u16x2 v;  // element-wise build lets the compiler load straight into each half
-            v.x = w.w0[row * kLdsPitch + i];
-            v.y = w.w1[row * kLdsPitch + i];
+            v.x = w.w0[row * Geometry<K>::pitch + i];
+            v.y = w.w1[row * Geometry<K>::pitch + i];
             out[i] = __builtin_bit_cast(uint32_t, v);
         }
         return;
@@ -609,8 +631,8 @@ __device__ __forceinline__ void load_pair_row(const PairRow &w, int row, uint32_
     uint32_t a[D], b[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        a[j] = w.q0[row * (kLdsPitch / 2) + j];
-        b[j] = w.q1[row * (kLdsPitch / 2) + j];
+        a[j] = w.q0[row * (Geometry<K>::pitch / 2) + j];
+        b[j] = w.q1[row * (Geometry<K>::pitch / 2) + j];
     }
     int n = 0;
     out[n++] = __builtin_amdgcn_perm(b[0], a[0], kHiHi);
@@ -666,7 +688,7 @@ __device__ __forceinline__ uint32_t select_blocks(const uint32_t *run, const Pai
 
 template <int K>
 __device__ __forceinline__ uint32_t median_pair(const uint16_t *tile, uint32_t o0, uint32_t o1) {
-    static_assert(kLdsPitch % 2 == 0, "window rows must keep their parity");
+    static_assert(Geometry<K>::pitch % 2 == 0, "window rows must keep their parity");
     uint32_t win[K * K];
     return select_blocks<K, 0, 0, (K * K - 1) / 2>(nullptr, pair_row(tile, o0, o1), win);
 }
@@ -683,10 +705,10 @@ __device__ __forceinline__ uint32_t median_registers(const uint16_t *w) {
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
         const int e0 = 2 * j, e1 = 2 * j + 1;
-        const uint32_t lo = w[(e0 / K) * kLdsPitch + e0 % K];
+        const uint32_t lo = w[(e0 / K) * Geometry<K>::pitch + e0 % K];
         // an odd element count leaves the last high half empty: it repeats the
         // last element, whose second copy is taken out of the count below
-        const uint32_t hi = e1 < N ? w[(e1 / K) * kLdsPitch + e1 % K] : lo;
+        const uint32_t hi = e1 < N ? w[(e1 / K) * Geometry<K>::pitch + e1 % K] : lo;
         v[j] = lo | (hi << 16);
     }
     uint32_t mn = 0xffffffffu, mx = 0u;
@@ -705,6 +727,84 @@ __device__ __forceinline__ uint32_t median_registers(const uint16_t *w) {
         for (int j = 0; j < NP; ++j) above = pk_add(above, pk_min(pk_subsat(v[j], tt), 0x00010001u));
         uint32_t gt = (above & 0xffffu) + (above >> 16);
         if ((N & 1) && pad > t) gt -= 1;
+        if (N - gt > rank)
+            hi = t;
+        else
+            lo = t + 1;
+    }
+    return lo;
+}
+
+// One window per group of lanes (windows above 15x15).  The group's L lanes
+// (8 up to 512 window values, else 16; aligned inside a 16-lane DPP row) hold
+// the window's values g, g + L, g + 2L, ... (S_xy order), two per VGPR, and run
+// the same grey-level bisection as median_registers with counts summed over
+// the group by DPP butterflies.  Registers past the window's end repeat its
+// first value, taken back out of every count.
+template <int K>
+struct GroupPlan {
+    static constexpr int N = K * K;
+    static constexpr int lanes = N <= 512 ? 8 : 16;
+    static constexpr int regs = (N + 2 * lanes - 1) / (2 * lanes);  // packed registers per lane
+    static constexpr int pad = 2 * lanes * regs - N;                // repeated values in the group
+    static_assert(K > lanes, "a lane's next value is at most one window row further");
+};
+
+// op over the aligned group of L lanes (L = 8 or 16), result in every lane.
+template <int L, typename Op>
+__device__ __forceinline__ uint32_t group_reduce(uint32_t v, Op op) {
+    static_assert(L == 8 || L == 16, "groups of 8 or 16 lanes");
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false));   // lane ^ 1
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false));   // lane ^ 2
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));  // 7 - lane in 8
+    if constexpr (L == 16)
+        v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));  // 15 - lane
+    return v;
+}
+
+// Median of the window whose top-left value is w, computed by the group
+// member g (0..L-1); every member returns it.
+template <int K>
+__device__ __forceinline__ uint32_t median_group(const uint16_t *w, int g) {
+    using P = GroupPlan<K>;
+    constexpr int N = P::N, L = P::lanes, pitch = Geometry<K>::pitch;
+    constexpr uint32_t rank = (N - 1) / 2;
+    const uint32_t first = w[0];
+    uint32_t v[P::regs];
+    int row = 0, col = g;  // g < L < K
+    auto next = [&](int idx) -> uint32_t {
+        uint32_t x = first;
+        if (idx * L + L <= N || idx * L + g < N) x = w[row * pitch + col];
+        col += L;
+        if (col >= K) {
+            col -= K;
+            ++row;
+        }
+        return x;
+    };
+#pragma unroll
+    for (int j = 0; j < P::regs; ++j) {
+        const uint32_t lo = next(2 * j);
+        const uint32_t hi = next(2 * j + 1);
+        v[j] = lo | (hi << 16);
+    }
+    uint32_t mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+    for (int j = 0; j < P::regs; ++j) {
+        mn = pk_min(mn, v[j]);
+        mx = pk_max(mx, v[j]);
+    }
+    uint32_t lo = group_reduce<L>(min(mn & 0xffffu, mn >> 16), [](uint32_t a, uint32_t b) { return min(a, b); });
+    uint32_t hi = group_reduce<L>(max(mx & 0xffffu, mx >> 16), [](uint32_t a, uint32_t b) { return max(a, b); });
+    while (lo < hi) {  // uniform over the group
+        const uint32_t t = (lo + hi) >> 1;
+        const uint32_t tt = t | (t << 16);
+        uint32_t above = 0;
+#pragma unroll
+        for (int j = 0; j < P::regs; ++j) above = pk_add(above, pk_min(pk_subsat(v[j], tt), 0x00010001u));
+        uint32_t gt = group_reduce<L>((above & 0xffffu) + (above >> 16),
+                                      [](uint32_t a, uint32_t b) { return a + b; });
+        if (first > t) gt -= P::pad;
         if (N - gt > rank)
             hi = t;
         else
@@ -790,7 +890,7 @@ __device__ __forceinline__ TileRange xcd_range(int b, int G, int total) {
 template <int K, int NT = kThreads>
 struct TileSmem {
     using G = Geometry<K, NT>;
-    uint16_t tile[G::rows * kLdsPitch];
+    uint16_t tile[G::rows * G::pitch];
     uint16_t list[G::tile_px];  // LDS offsets of flagged centres, then their medians
     uint32_t count;             // list length
 };
@@ -807,8 +907,8 @@ template <int K, int NT, int SEL>
 __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32_t flags, int centre0,
                                                      int rot) {
     using G = Geometry<K, NT>;
-    static_assert(SEL == kSelectBisect || (SEL == kSelectNetwork && K <= kNetworkMaxWindow),
-                  "no selection network for this window");
+    static_assert(SEL == kSelectGroup || (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
+                  "no kernel of this selection for this window");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const uint32_t cnt = __builtin_popcount(flags);
@@ -824,7 +924,7 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
         while (m) {
             const int b = __builtin_ctz(m);
             m &= m - 1;
-            sm.list[j++] = (uint16_t)(centre0 + bit_row(b) * kLdsPitch + bit_col(b));
+            sm.list[j++] = (uint16_t)(centre0 + bit_row(b) * G::pitch + bit_col(b));
         }
     }
     __syncthreads();
@@ -832,9 +932,20 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
     // 4. medians, two list entries per lane, consecutive lanes first so that as
     //    few waves as possible run the selection; which wave starts the list
     //    rotates with `rot` (waves sit on fixed SIMDs)
-    constexpr int corner = G::r * kLdsPitch + G::r;
+    constexpr int corner = G::r * G::pitch + G::r;
     const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)rot) % NT;
-    if constexpr (SEL == kSelectBisect) {
+    if constexpr (SEL == kSelectGroup) {
+        // one window per group of lanes: all lanes of a group read the entry
+        // before its first lane overwrites it (a group lies inside one wave)
+        constexpr int L = GroupPlan<K>::lanes, NG = NT / L;
+        const int g = tid % L;
+        const uint32_t gslot = ((uint32_t)(tid / L) + (64u / L) * (uint32_t)rot) % NG;
+        for (uint32_t i = gslot; i < total; i += NG) {
+            const uint32_t e0 = sm.list[i];
+            const uint32_t med = median_group<K>(sm.tile + e0 - corner, g);
+            if (g == 0) sm.list[i] = (uint16_t)med;
+        }
+    } else if constexpr (SEL == kSelectBisect) {
         // one window per lane
         for (uint32_t i = slot; i < total; i += NT) {
             const uint32_t e0 = sm.list[i];
@@ -856,7 +967,7 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
         while (m) {
             const int b = __builtin_ctz(m);
             m &= m - 1;
-            sm.tile[centre0 + bit_row(b) * kLdsPitch + bit_col(b)] = sm.list[j++];
+            sm.tile[centre0 + bit_row(b) * G::pitch + bit_col(b)] = sm.list[j++];
         }
     }
     return wave_total;
@@ -868,8 +979,8 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
 template <typename T, int K, int MODE, int NT = kThreads, int SEL = default_select(K)>
 __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K, NT> &sm) {
     using G = Geometry<K, NT>;
-    static_assert(SEL == kSelectBisect || (SEL == kSelectNetwork && K <= kNetworkMaxWindow),
-                  "no selection network for this window");
+    static_assert(SEL == kSelectGroup || (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
+                  "no kernel of this selection for this window");
     constexpr int R = G::R;
     const int f = tile / a.tiles_per_frame;
     const int rem = tile - f * a.tiles_per_frame;
@@ -924,7 +1035,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         }
         return wave_total;
     } else {
-        const int centre0 = (strip * R + G::r) * kLdsPitch + kHalo + 4 * tx;
+        const int centre0 = (strip * R + G::r) * G::pitch + G::halo + 4 * tx;
         const uint32_t wave_total = median_into_tile<K, NT, SEL>(sm, flags, centre0, tile);
         // 5. store the thread's block (its own LDS values only: no barrier needed)
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
@@ -932,7 +1043,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if (!full && py + q >= H) break;
-            const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * kLdsPitch);
+            const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * G::pitch);
             const uint32_t ro = __umul24((uint32_t)(py + q), (uint32_t)a.dst_pitch);
             if (full) {
                 const uint32_t off = ro + (uint32_t)px * (uint32_t)sizeof(T);

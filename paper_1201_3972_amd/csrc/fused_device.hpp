@@ -28,7 +28,7 @@ struct FusedGeometry {
     using G = Geometry<K, NT>;
     static constexpr int out_rows = G::TH - 2 * G::r;  // pass-2 output rows per tile
     static_assert(K <= kFusedMaxWindow && G::r <= 4, "pass-1 ring of 4 columns covers r <= 4");
-    static_assert(kHalo >= 2 * G::r, "the input halo covers both passes");
+    static_assert(G::halo >= 2 * G::r, "the input halo covers both passes");
 };
 
 // Persistent kernel over fused tiles.  Tile t of frame f has its output origin
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
     const int W = a.width, H = a.height;
     const int tid = threadIdx.x;
     const int tx = tid % kThreadsX, strip = tid / kThreadsX;
-    const int centre0 = (strip * R + r) * kLdsPitch + kHalo + 4 * tx;
+    const int centre0 = (strip * R + r) * G::pitch + G::halo + 4 * tx;
     uint32_t n1 = 0, n2 = 0;  // this thread's output pixels flagged by pass 1 and pass 2
     for (int t = rg.first; t < rg.end; t += rg.stride) {
         const int f = t / a.tiles_per_frame;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
                 m &= m - 1;
                 const int col = bit_col(b), row = bit_row(b);
                 const int cx = min(max(px + col, 0), W - 1), cy = min(max(py + row, 0), H - 1);
-                sm.tile[centre0 + row * kLdsPitch + col] = sm.tile[centre0 + (cy - py) * kLdsPitch + (cx - px)];
+                sm.tile[centre0 + row * G::pitch + col] = sm.tile[centre0 + (cy - py) * G::pitch + (cx - px)];
             }
             __syncthreads();
         }
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 if (((out >> q) & 1u) == 0) continue;
-                const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * kLdsPitch);
+                const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * G::pitch);
                 const uint32_t ro = __umul24((uint32_t)(py + q), (uint32_t)a.dst_pitch);
                 store4<T>(dst, ro, px, xend, aligned, c[0], c[1]);
             }

@@ -38,6 +38,13 @@ inline irf_status check_common(int width, int height, int nframes, irf_dtype dty
     return IRF_OK;
 }
 
+// Batch plans and the server run windows up to IRF_MAX_BATCH_WINDOW.
+inline irf_status check_batch_frame(int width, int height, irf_dtype dtype, int window) {
+    const irf_status st = check_common(width, height, 1, dtype, window);
+    if (st) return st;
+    return window > IRF_MAX_BATCH_WINDOW ? IRF_ERR_WINDOW : IRF_OK;
+}
+
 // Device code addresses a frame with 32-bit byte offsets from its base and
 // 24-bit row multiplies: a pitch must stay below 2^24 bytes and a frame's span
 // below 4 GiB.

@@ -24,12 +24,13 @@ constexpr int kVersion = (1 << 16) | 0;
 // Tuning table of the single-size kernels, per pixel type and window: 0 means
 // the untuned default, otherwise threads | select << 16.  Entries change only
 // through ir_filter_set_tuning; a launch reads its entry once.
-std::atomic<uint32_t> g_tuning[2][8];
+constexpr int kWindowSlots = (IRF_MAX_WINDOW - 3) / 2 + 1;
+std::atomic<uint32_t> g_tuning[2][kWindowSlots];
 
 // Fusion of pass pairs, per pixel type and window: 0 means automatic (the
 // default), 1 runs every pass as its own launch, otherwise the fused kernel's
 // workgroup size.
-std::atomic<uint32_t> g_fusion[2][8];
+std::atomic<uint32_t> g_fusion[2][kWindowSlots];
 
 int window_slot(int window) { return (window - 3) / 2; }
 
@@ -269,7 +270,7 @@ const char *ir_filter_status_string(irf_status s) {
         case IRF_ERR_DIMS: return "invalid dimensions";
         case IRF_ERR_PITCH: return "pitch or stride too small";
         case IRF_ERR_DTYPE: return "unsupported pixel type";
-        case IRF_ERR_WINDOW: return "window must be odd and within 3..15";
+        case IRF_ERR_WINDOW: return "window must be odd and within 3..31 (3..15 for batches)";
         case IRF_ERR_PASSES: return "invalid pass count or missing scratch";
         case IRF_ERR_ALIAS: return "output overlaps an input";
         case IRF_ERR_HIP: return "HIP error";

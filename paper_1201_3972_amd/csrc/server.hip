@@ -371,7 +371,7 @@ irf_status ir_filter_server_submit(irf_server *s, const irf_request *reqs, int n
     for (int i = 0; i < n; ++i) {
         const irf_request &r = reqs[i];
         if (!r.host_src || !r.host_dst) return IRF_ERR_NULL;
-        irf_status st = irf::host::check_common(r.width, r.height, 1, r.dtype, r.window);
+        irf_status st = irf::host::check_batch_frame(r.width, r.height, r.dtype, r.window);
         if (st) return st;
         const int b = bytes_of(r.dtype);
         if ((st = irf::host::check_layout(r.src_pitch, 0, r.width, r.height, 1, b))) return st;

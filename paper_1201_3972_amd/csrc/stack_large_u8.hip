@@ -1,0 +1,9 @@
+// stack_large_u8.hip -- the 8-bit instantiations of the single-size kernels
+// for windows 17x17 to 31x31 (group bisection).
+#include "stack_launch.hpp"
+
+namespace irf {
+bool launch_stack_large_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s) {
+    return stack_impl::launch_stack<uint8_t, true>(window, mode, t, a, s);
+}
+}  // namespace irf

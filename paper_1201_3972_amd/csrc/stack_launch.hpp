@@ -22,17 +22,21 @@ struct Tuning {
 inline Tuning default_tuning(int window) { return {default_threads(window), default_select(window)}; }
 
 // Whether a kernel exists for (window, tuning): 128 or 256 threads; networks
-// for windows up to 11x11, bisection for every window.
+// and one-lane bisection up to 15x15, group bisection above.
 inline bool tuning_available(int window, Tuning t) {
     if (t.threads != 128 && t.threads != 256) return false;
-    if (t.select == kSelectNetwork) return window <= kNetworkMaxWindow;
-    return t.select == kSelectBisect;
+    if (window <= kNetworkMaxWindow) return t.select == kSelectNetwork || t.select == kSelectBisect;
+    return t.select == kSelectGroup;
 }
 
 // Launch the stack kernel of the pixel type for a.total_tiles tiles; false if
-// the combination has no kernel (nothing is launched then).
+// the combination has no kernel (nothing is launched then).  Windows above
+// 15x15 go to launch_stack_large_*, instantiated in their own translation
+// units (stack_large_u8.hip, stack_large_u16.hip).
 bool launch_stack_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
 bool launch_stack_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
+bool launch_stack_large_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
+bool launch_stack_large_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
 
 // Two passes in one launch (fused.hip): windows up to 9x9, workgroups of 256 or
 // 512 threads (blocks of 128 x 64 or 128 x 128 pixels).
@@ -102,6 +106,10 @@ bool launch_threads(int select, const StackArgs &a, hipStream_t s) {
     if constexpr (MODE == MODE_DETECT) {
         launch_variant<T, K, MODE, NT, default_select(K)>(a, s);
         return true;
+    } else if constexpr (K > kNetworkMaxWindow) {
+        if (select != kSelectGroup) return false;
+        launch_variant<T, K, MODE, NT, kSelectGroup>(a, s);
+        return true;
     } else {
         if (select == kSelectBisect) {
             launch_variant<T, K, MODE, NT, kSelectBisect>(a, s);
@@ -124,27 +132,42 @@ bool launch_tuned(Tuning t, const StackArgs &a, hipStream_t s) {
     return false;
 }
 
-template <typename T, int MODE>
+// LARGE: the windows above 15x15, else those up to it.
+template <typename T, int MODE, bool LARGE>
 bool launch_window(int window, Tuning t, const StackArgs &a, hipStream_t s) {
-    switch (window) {
-        case 3: return launch_tuned<T, 3, MODE>(t, a, s);
-        case 5: return launch_tuned<T, 5, MODE>(t, a, s);
-        case 7: return launch_tuned<T, 7, MODE>(t, a, s);
-        case 9: return launch_tuned<T, 9, MODE>(t, a, s);
-        case 11: return launch_tuned<T, 11, MODE>(t, a, s);
-        case 13: return launch_tuned<T, 13, MODE>(t, a, s);
-        case 15: return launch_tuned<T, 15, MODE>(t, a, s);
-        default: return false;
+    if constexpr (!LARGE) {
+        switch (window) {
+            case 3: return launch_tuned<T, 3, MODE>(t, a, s);
+            case 5: return launch_tuned<T, 5, MODE>(t, a, s);
+            case 7: return launch_tuned<T, 7, MODE>(t, a, s);
+            case 9: return launch_tuned<T, 9, MODE>(t, a, s);
+            case 11: return launch_tuned<T, 11, MODE>(t, a, s);
+            case 13: return launch_tuned<T, 13, MODE>(t, a, s);
+            case 15: return launch_tuned<T, 15, MODE>(t, a, s);
+            default: return false;
+        }
+    } else {
+        switch (window) {
+            case 17: return launch_tuned<T, 17, MODE>(t, a, s);
+            case 19: return launch_tuned<T, 19, MODE>(t, a, s);
+            case 21: return launch_tuned<T, 21, MODE>(t, a, s);
+            case 23: return launch_tuned<T, 23, MODE>(t, a, s);
+            case 25: return launch_tuned<T, 25, MODE>(t, a, s);
+            case 27: return launch_tuned<T, 27, MODE>(t, a, s);
+            case 29: return launch_tuned<T, 29, MODE>(t, a, s);
+            case 31: return launch_tuned<T, 31, MODE>(t, a, s);
+            default: return false;
+        }
     }
 }
 
-template <typename T>
+template <typename T, bool LARGE>
 bool launch_stack(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s) {
     switch (mode) {
-        case MODE_DETECT: return launch_window<T, MODE_DETECT>(window, t, a, s);
-        case MODE_FNR: return launch_window<T, MODE_FNR>(window, t, a, s);
-        case MODE_MEDIAN_MASK: return launch_window<T, MODE_MEDIAN_MASK>(window, t, a, s);
-        case MODE_MEDIAN_ALL: return launch_window<T, MODE_MEDIAN_ALL>(window, t, a, s);
+        case MODE_DETECT: return launch_window<T, MODE_DETECT, LARGE>(window, t, a, s);
+        case MODE_FNR: return launch_window<T, MODE_FNR, LARGE>(window, t, a, s);
+        case MODE_MEDIAN_MASK: return launch_window<T, MODE_MEDIAN_MASK, LARGE>(window, t, a, s);
+        case MODE_MEDIAN_ALL: return launch_window<T, MODE_MEDIAN_ALL, LARGE>(window, t, a, s);
         default: return false;
     }
 }

@@ -66,7 +66,10 @@ SIGNATURES = {
 
 IRF_SELECT_NETWORK = 1
 IRF_SELECT_BISECT = 2
-SELECT_NAMES = {IRF_SELECT_NETWORK: "network", IRF_SELECT_BISECT: "bisect"}
+IRF_SELECT_GROUP = 3
+SELECT_NAMES = {IRF_SELECT_NETWORK: "network", IRF_SELECT_BISECT: "bisect", IRF_SELECT_GROUP: "group"}
+MAX_WINDOW = 31        # single-size entry points
+MAX_BATCH_WINDOW = 15  # batch plans and the server
 
 
 IRF_PLAN_GRAPH = 1

@@ -24,7 +24,7 @@ def lib():
 def _restore_defaults():
     yield
     for dt in ("u8", "u16"):
-        for k in range(3, 16, 2):
+        for k in range(3, 32, 2):
             irfilter.set_tuning(dt, k, 0, 0)
             irfilter.set_fusion(dt, k, -1)
     irfilter.set_batch_threads(0)
@@ -35,6 +35,8 @@ def test_defaults():
         for k in (3, 5, 9, 11, 13, 15):
             assert irfilter.get_tuning(dt, k) == (128, irfilter.IRF_SELECT_NETWORK)
         assert irfilter.get_tuning(dt, 7) == (256, irfilter.IRF_SELECT_NETWORK)
+        for k in range(17, 32, 2):
+            assert irfilter.get_tuning(dt, k) == (256, irfilter.IRF_SELECT_GROUP)
     assert irfilter.get_batch_threads() == 128
 
 
@@ -52,7 +54,10 @@ def test_set_get_and_restore():
     (("u16", 5, 128, 3), -11),
     (("u16", 5, 128, 0), -11),
     (("u16", 4, 128, 1), -5),
-    (("u16", 17, 128, 1), -5),
+    (("u16", 33, 128, 1), -5),
+    (("u16", 17, 128, 1), -11),  # no network above 15x15
+    (("u16", 17, 128, 2), -11),  # nor one-lane bisection
+    (("u16", 5, 128, 3), -11),   # group bisection only above 15x15
 ])
 def test_invalid_tuning(args, status):
     dt, k, t, sel = args
@@ -128,7 +133,7 @@ def test_resolve_fusion_follows_the_setting():
 
 @pytest.mark.parametrize("dt,k,threads,status", [
     ("u16", 11, 256, -11), ("u16", 15, 512, -11), ("u16", 5, 128, -11), ("u16", 5, 1, -11),
-    ("u16", 5, -2, -11), ("u16", 4, 256, -5), ("u16", 17, 0, -5),
+    ("u16", 5, -2, -11), ("u16", 4, 256, -5), ("u16", 33, 0, -5), ("u16", 17, 256, -11),
 ])
 def test_invalid_fusion(dt, k, threads, status):
     lib = irfilter.load()
@@ -181,3 +186,7 @@ def test_candidates_cover_every_available_kernel():
         c = autotune.candidates(k)
         assert (128, irfilter.IRF_SELECT_NETWORK) in c and (256, irfilter.IRF_SELECT_BISECT) in c
         assert len(c) == 4
+    for k in autotune.LARGE_WINDOWS:
+        assert autotune.candidates(k) == [(128, irfilter.IRF_SELECT_GROUP), (256, irfilter.IRF_SELECT_GROUP)]
+        irfilter.set_tuning("u8", k, 256, irfilter.IRF_SELECT_GROUP)
+        assert irfilter.get_tuning("u8", k) == (256, irfilter.IRF_SELECT_GROUP)

@@ -375,6 +375,56 @@ def section_f1(torch, irfilter, synth, oracle, dev, rounds: int = 5, reps: int =
     return out
 
 
+def section_f2(torch, irfilter, synth, oracle, dev, frames: int = 8, reps: int = 3) -> dict:
+    """Windows above 15x15 (17x17 .. 31x31, lane-group bisection) on a stack of
+    1920x1080 u16 frames with 40 % mixed impulses, 15x15 (networks) beside them:
+    ms per frame.  Parity: a whole 480x270 frame of the same recipe against the
+    oracle, and 512 sampled pixels of the timed stack against the oracle's
+    pointwise evaluation."""
+    windows = (15, 17, 19, 21, 23, 25, 27, 29, 31)
+    f = synth.make_frame(synth.c3_spec(0))
+    small = synth.make_frame(synth.FrameSpec(480, 270, "u16", "mixed", 0.40, 20.0, synth.config_seed(8)))
+    H, W = f.shape
+    src = torch.empty((frames, H, W), dtype=torch.uint16, device=dev)
+    one = to_dev(torch, f, dev)
+    for i in range(frames):
+        src[i].copy_(one)
+    dst = torch.empty_like(src)
+    s_src = to_dev(torch, small, dev)
+    s_dst = torch.empty_like(s_src)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    rng = np.random.default_rng(1080)
+    pts = [(int(x), int(y)) for x, y in zip(rng.integers(0, W, 512), rng.integers(0, H, 512))]
+    pts += [(0, 0), (W - 1, H - 1), (W - 1, 0), (0, H - 1)]
+    out = {"workload": f"{frames} x 1920x1080 u16, 40% mixed impulses (as the 1080p sweep), one launch per window",
+           "windows": {}}
+    for k in windows:
+        irfilter.ir_filter_run(s_src, s_dst, k, flagged_count=cnt)
+        torch.cuda.synchronize()
+        want, wc = oracle.fnr(small, k)
+        if not np.array_equal(s_dst.view(torch.int16).cpu().numpy().view(np.uint16), want) or \
+                int(cnt.item()) != int(wc[0]):
+            raise RuntimeError(f"f2 {k}x{k}: 480x270 frame differs from the oracle")
+        irfilter.ir_filter_run_frames(src, dst, k, flagged_count=cnt)
+        torch.cuda.synchronize()
+        flagged = int(cnt.item())
+        wpts = oracle.fnr_at(f, k, pts)
+        for i in (0, frames - 1):
+            got = dst[i].view(torch.int16).cpu().numpy().view(np.uint16)
+            if not np.array_equal(np.array([got[y, x] for x, y in pts], dtype=np.uint32), wpts):
+                raise RuntimeError(f"f2 {k}x{k}: sampled pixels of frame {i} differ from the oracle")
+        best = float("inf")
+        for _ in range(reps):
+            best = min(best, _timed(torch, lambda: irfilter.ir_filter_run_frames(src, dst, k), 2))
+        th, sel = irfilter.get_tuning("u16", k)
+        out["windows"][str(k)] = {"ms_per_frame": round(best / frames, 4),
+                                  "mpx_per_s": round(frames * W * H / best / 1e3, 1),
+                                  "flagged_fraction": round(flagged / (frames * W * H), 4),
+                                  "threads": th, "select": irfilter.SELECT_NAMES[sel]}
+        log(f"f2 {k}x{k}: {out['windows'][str(k)]}")
+    return out
+
+
 def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
     sections = {}
     wanted = [x for x in args.sections.split(",") if x and x != "none"]
@@ -391,6 +441,8 @@ def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
             sections["c5_serving"] = section_c5(torch, serving, dev)
         elif name == "f1":
             sections["f1_fused_two_passes"] = section_f1(torch, irfilter, synth, oracle, dev)
+        elif name == "f2":
+            sections["f2_large_windows"] = section_f2(torch, irfilter, synth, oracle, dev)
         elif name == "f3":
             sections["f3_table1_analogue"] = section_f3(torch, irfilter, synth, oracle, dev)
         log(f"section {name}: {time.perf_counter() - t1:.1f}s")
@@ -408,7 +460,7 @@ def main() -> int:
     ap.add_argument("--no-per-frame", action="store_true", help="skip the per-frame launch baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--sections", default="c1,c3,c4,c5,f1,f3",
+    ap.add_argument("--sections", default="c1,c3,c4,c5,f1,f2,f3",
                     help="extra workloads reported beside the headline (comma list, or 'none')")
     ap.add_argument("--no-headline", action="store_true",
                     help="run only the --sections workloads (for profiling them) and print their JSON")

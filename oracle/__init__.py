@@ -175,3 +175,21 @@ def fnr(frame: np.ndarray, k: int, passes: int = 1,
     if rc:
         raise ValueError(f"oracle_fnr rejected its arguments ({rc})")
     return out, counts
+
+
+def fnr_at(frame: np.ndarray, k: int, points) -> np.ndarray:
+    """One FNR pass evaluated at the (x, y) pixels in ``points`` only, each from
+    its own window: the centre value unless it equals the minimum or maximum of
+    S_xy (Section 3.3, Eq. 3a/3b), else element (k*k - 1)/2 of S_xy sorted by the
+    oracle's introsort (Section 3.4).  For sampled checks of frames too large
+    for :func:`fnr`."""
+    f, _ = _frame(frame)
+    out = np.zeros(len(points), dtype=np.uint32)
+    for i, (x, y) in enumerate(points):
+        S = window(f, int(x), int(y), k)
+        c = int(f[y, x])
+        if c == int(S.min()) or c == int(S.max()):
+            out[i] = introsort(S)[0][(k * k - 1) // 2]
+        else:
+            out[i] = c
+    return out

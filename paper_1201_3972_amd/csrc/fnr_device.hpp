@@ -696,9 +696,10 @@ __device__ __forceinline__ uint32_t median_pair(const uint16_t *tile, uint32_t o
 // One window per lane held in registers (the default for 13x13 and 15x15), two
 // window values per VGPR: a bisection on grey level over [g_min, g_max] counts
 // the values above the probe with three packed operations per register and
-// round (the window is read from LDS once).
+// round (the window is read from LDS once).  pk_one = 0x00010001 from the host
+// (a literal lets the compiler split the packed count into per-half compares).
 template <int K>
-__device__ __forceinline__ uint32_t median_registers(const uint16_t *w) {
+__device__ __forceinline__ uint32_t median_registers(const uint16_t *w, uint32_t pk_one) {
     constexpr int N = K * K, NP = (N + 1) / 2;
     constexpr uint32_t rank = (N - 1) / 2;
     uint32_t v[NP];
@@ -724,7 +725,7 @@ __device__ __forceinline__ uint32_t median_registers(const uint16_t *w) {
         const uint32_t tt = t | (t << 16);
         uint32_t above = 0;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) above = pk_add(above, pk_min(pk_subsat(v[j], tt), 0x00010001u));
+        for (int j = 0; j < NP; ++j) above = pk_add(above, pk_min(pk_subsat(v[j], tt), pk_one));
         uint32_t gt = (above & 0xffffu) + (above >> 16);
         if ((N & 1) && pad > t) gt -= 1;
         if (N - gt > rank)
@@ -763,9 +764,9 @@ __device__ __forceinline__ uint32_t group_reduce(uint32_t v, Op op) {
 }
 
 // Median of the window whose top-left value is w, computed by the group
-// member g (0..L-1); every member returns it.
+// member g (0..L-1); every member returns it.  pk_one as for median_registers.
 template <int K>
-__device__ __forceinline__ uint32_t median_group(const uint16_t *w, int g) {
+__device__ __forceinline__ uint32_t median_group(const uint16_t *w, int g, uint32_t pk_one) {
     using P = GroupPlan<K>;
     constexpr int N = P::N, L = P::lanes, pitch = Geometry<K>::pitch;
     constexpr uint32_t rank = (N - 1) / 2;
@@ -801,7 +802,7 @@ __device__ __forceinline__ uint32_t median_group(const uint16_t *w, int g) {
         const uint32_t tt = t | (t << 16);
         uint32_t above = 0;
 #pragma unroll
-        for (int j = 0; j < P::regs; ++j) above = pk_add(above, pk_min(pk_subsat(v[j], tt), 0x00010001u));
+        for (int j = 0; j < P::regs; ++j) above = pk_add(above, pk_min(pk_subsat(v[j], tt), pk_one));
         uint32_t gt = group_reduce<L>((above & 0xffffu) + (above >> 16),
                                       [](uint32_t a, uint32_t b) { return a + b; });
         if (first > t) gt -= P::pad;
@@ -901,11 +902,12 @@ struct TileSmem {
 // thread writes its own medians back into the tile.  sm.count must be 0, and
 // visible to every thread, on entry.  On return the tile holds the results at
 // the calling thread's pixels only: reading another thread's pixels needs a
-// barrier first.  `rot` rotates which wave starts the list.  Returns the
-// number of flagged pixels of the calling wave (wave-uniform).
+// barrier first.  `rot` rotates which wave starts the list; pk_one is the
+// host's 0x00010001 (see median_registers).  Returns the number of flagged
+// pixels of the calling wave (wave-uniform).
 template <int K, int NT, int SEL>
 __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32_t flags, int centre0,
-                                                     int rot) {
+                                                     int rot, uint32_t pk_one) {
     using G = Geometry<K, NT>;
     static_assert(SEL == kSelectGroup || (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
                   "no kernel of this selection for this window");
@@ -942,14 +944,14 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
         const uint32_t gslot = ((uint32_t)(tid / L) + (64u / L) * (uint32_t)rot) % NG;
         for (uint32_t i = gslot; i < total; i += NG) {
             const uint32_t e0 = sm.list[i];
-            const uint32_t med = median_group<K>(sm.tile + e0 - corner, g);
+            const uint32_t med = median_group<K>(sm.tile + e0 - corner, g, pk_one);
             if (g == 0) sm.list[i] = (uint16_t)med;
         }
     } else if constexpr (SEL == kSelectBisect) {
         // one window per lane
         for (uint32_t i = slot; i < total; i += NT) {
             const uint32_t e0 = sm.list[i];
-            sm.list[i] = (uint16_t)median_registers<K>(sm.tile + e0 - corner);
+            sm.list[i] = (uint16_t)median_registers<K>(sm.tile + e0 - corner, pk_one);
         }
     } else {
         for (uint32_t i = 2 * slot; i < total; i += 2 * NT) {
@@ -1036,7 +1038,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         return wave_total;
     } else {
         const int centre0 = (strip * R + G::r) * G::pitch + G::halo + 4 * tx;
-        const uint32_t wave_total = median_into_tile<K, NT, SEL>(sm, flags, centre0, tile);
+        const uint32_t wave_total = median_into_tile<K, NT, SEL>(sm, flags, centre0, tile, a.pk_one);
         // 5. store the thread's block (its own LDS values only: no barrier needed)
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
         const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform

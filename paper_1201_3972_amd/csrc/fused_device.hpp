@@ -67,7 +67,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
         // pass 1 on every frame pixel of the block
         const uint32_t f1 = detect_block<K>(sm.tile, strip, tx, a.pk_one) & in_frame;
         n1 += __builtin_popcount(f1 & out);
-        median_into_tile<K, NT, SEL>(sm, f1, centre0, t);
+        median_into_tile<K, NT, SEL>(sm, f1, centre0, t, a.pk_one);
         if (tid == 0) sm.count = 0;  // every thread read the pass-1 list length before its selection
         __syncthreads();
 
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
         // pass 2 on the output pixels
         const uint32_t f2 = detect_block<K>(sm.tile, strip, tx, a.pk_one) & out;
         n2 += __builtin_popcount(f2);
-        median_into_tile<K, NT, SEL>(sm, f2, centre0, t);
+        median_into_tile<K, NT, SEL>(sm, f2, centre0, t, a.pk_one);
 
         // store the thread's output pixels (a thread holds whole 4-column groups
         // of the output, or none; the last tile of a row may end inside one)

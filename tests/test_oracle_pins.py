@@ -203,6 +203,28 @@ def test_plain_median_filter_matches_scipy(k):
     assert sorts == f.size
 
 
+@pytest.mark.parametrize("k", [17, 25, 31])
+def test_large_windows_match_scipy(k):
+    # the windows above 15x15: detector and median against scipy's separable
+    # min/max and median filters with replicated borders
+    f = synth.make_frame(synth.FrameSpec(83, 59, "u16", "mixed", 0.4, 20.0, 90 + k))
+    want, flag = scipy_pass(f, k)
+    got, counts = oracle.fnr(f, k)
+    np.testing.assert_array_equal(got, want)
+    assert int(counts[0]) == int(flag.sum())
+    np.testing.assert_array_equal(oracle.median(f, k)[0], ndi.median_filter(f, size=k, mode="nearest"))
+
+
+def test_pointwise_evaluation_equals_the_whole_pass():
+    f = synth.make_frame(synth.FrameSpec(70, 45, "u8", "mixed", 0.4, 0.0, 19))
+    rng = np.random.default_rng(8)
+    pts = [(int(x), int(y)) for x, y in zip(rng.integers(0, 70, 150), rng.integers(0, 45, 150))]
+    pts += [(0, 0), (69, 44), (0, 44), (69, 0)]
+    for k in (3, 9, 21):
+        whole, _ = oracle.fnr(f, k)
+        np.testing.assert_array_equal(oracle.fnr_at(f, k, pts), [whole[y, x] for x, y in pts])
+
+
 def test_masked_median_matches_scipy():
     rng = np.random.default_rng(3)
     f = synth.make_frame(synth.FrameSpec(64, 48, "u8", "rv", 0.3, 0.0, 5))

@@ -57,6 +57,8 @@ def _configure(lib):
     lib.oracle_median.restype = i32
     lib.oracle_fnr.argtypes = [vp, sz, vp, sz, i32, i32, i32, i32, i32, vp, vp]
     lib.oracle_fnr.restype = i32
+    lib.oracle_detect_directional.argtypes = [vp, sz, vp, sz, i32, i32, i32, vp]
+    lib.oracle_detect_directional.restype = i32
     return lib
 
 
@@ -140,6 +142,22 @@ def detect(frame: np.ndarray, k: int) -> Tuple[np.ndarray, int]:
                                ctypes.byref(cnt))
     if rc:
         raise ValueError(f"oracle_detect rejected its arguments ({rc})")
+    return mask, int(cnt.value)
+
+
+def detect_directional(frame: np.ndarray) -> Tuple[np.ndarray, int]:
+    """Opt-in directional detector, a reading of Fig. 1's caption (not the
+    paper's detector): a pixel is noisy when, on each of the four lines through
+    it in its 3x3 window (row, column, both diagonals), its grey level lies
+    outside the range of its two neighbours.  Returns (mask, count)."""
+    f, b = _frame(frame)
+    H, W = f.shape
+    mask = np.zeros((H, W), dtype=np.uint8)
+    cnt = ctypes.c_uint64(0)
+    rc = _load().oracle_detect_directional(_ptr(f), f.strides[0], _ptr(mask), mask.strides[0], W, H, b,
+                                           ctypes.byref(cnt))
+    if rc:
+        raise ValueError(f"oracle_detect_directional rejected its arguments ({rc})")
     return mask, int(cnt.value)
 
 

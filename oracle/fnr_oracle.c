@@ -391,3 +391,49 @@ int oracle_fnr(const void *src, size_t src_pitch, void *dst, size_t dst_pitch, i
     free(S);
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Directional detector (opt-in; a reading of Fig. 1's caption).             */
+/* ------------------------------------------------------------------------- */
+/*
+ * Section 3 argues that the grey level of a signal pixel varies monotonically
+ * along the object's surface while an impulse cannot, and the caption of
+ * Fig. 1 (the figure itself is missing) compares the central pixel with its two
+ * neighbours in the 3 x 3 window.  Reading taken here: the four lines through
+ * the centre of the 3 x 3 S_xy are the row, the column and the two diagonals;
+ * the centre is monotone along a line when its grey level lies between the two
+ * neighbours on that line (min <= g(x, y) <= max, ties included), and the pixel
+ * is noisy when it is monotone along none of the four.  Neighbours outside the
+ * frame are clamped as everywhere else.  The paper does not fix this rule: only
+ * the min/max detector above is the paper's.
+ */
+static int between(px_t c, px_t a, px_t b) {
+    px_t lo = a < b ? a : b, hi = a < b ? b : a;
+    return lo <= c && c <= hi;
+}
+
+int oracle_detect_directional(const void *src, size_t src_pitch, uint8_t *mask, size_t mask_pitch,
+                              int W, int H, int bytes, uint64_t *count) {
+    if (check_frame(src, src_pitch, W, H, bytes)) return ORACLE_EINVAL;
+    if (!mask || mask_pitch < (size_t)W) return ORACLE_EINVAL;
+    px_t *A = (px_t *)malloc(sizeof(px_t) * (size_t)W * H);
+    if (!A) return ORACLE_ENOMEM;
+    read_frame(src, src_pitch, W, H, bytes, A);
+    px_t S[9]; /* S_xy of the 3 x 3 window in the paper's listing order */
+    uint64_t c = 0;
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            gather_window(A, W, H, x, y, 3, S);
+            const px_t g = S[4];
+            /* row (S[3], S[5]), column (S[1], S[7]), diagonal (S[0], S[8]),
+               anti-diagonal (S[2], S[6]) */
+            const int monotone = between(g, S[3], S[5]) || between(g, S[1], S[7]) ||
+                                 between(g, S[0], S[8]) || between(g, S[2], S[6]);
+            mask[(size_t)y * mask_pitch + x] = monotone ? 0 : 1;
+            c += monotone ? 0 : 1;
+        }
+    }
+    if (count) *count = c;
+    free(A);
+    return ORACLE_OK;
+}

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests import test_oracle_directional as dpins
 from tests import test_oracle_pins as pins
 
 MUTANTS = {
@@ -54,6 +55,21 @@ MUTANTS = {
                          "                A[(size_t)y * W + x] = v & 0x3FFF;"),
 }
 
+# the opt-in directional detector (its own pins, test_oracle_directional.py)
+DIRECTIONAL_MUTANTS = {
+    # ties left out of the range (strict inequalities)
+    "dir_strict_range": ("return lo <= c && c <= hi;", "return lo < c && c < hi;"),
+    # noisy when non-monotone along any line instead of every line
+    "dir_any_line": ("between(g, S[3], S[5]) || between(g, S[1], S[7]) ||",
+                     "between(g, S[3], S[5]) && between(g, S[1], S[7]) &&"),
+    # a diagonal paired with the wrong neighbour
+    "dir_wrong_pair": ("between(g, S[0], S[8]) || between(g, S[2], S[6]);",
+                       "between(g, S[0], S[2]) || between(g, S[6], S[8]);"),
+    # the column line dropped
+    "dir_column_dropped": ("between(g, S[3], S[5]) || between(g, S[1], S[7]) ||",
+                           "between(g, S[3], S[5]) ||"),
+}
+
 
 def _run_pins():
     """The pin subset run against each build; raises AssertionError on a miss."""
@@ -70,10 +86,36 @@ def _run_pins():
     pins.test_introsort_takes_the_quicksort_branch_for_windows_above_16()
 
 
+def _run_directional_pins():
+    for dt in (np.uint8, np.uint16):
+        dpins.test_constant_frames_have_no_noise(dt)
+    dpins.test_ramps_in_every_direction_have_no_noise()
+    for val in (0, 255):
+        dpins.test_interior_impulses_are_the_only_noise(val)
+    dpins.test_one_pixel_lines_are_kept_while_the_extreme_detector_flags_them()
+    dpins.test_border_pixels_are_never_noise()
+    dpins.test_strict_extremes_are_noise_and_noise_differs_from_all_neighbours()
+    for seed in range(6):
+        dpins.test_dihedral_symmetry(seed)
+    dpins.test_monotone_maps_and_complement_keep_the_flags()
+
+
 def test_unmutated_source_passes_the_subset(tmp_path):
     lib = oracle.compile_source(oracle.source_text(), str(tmp_path / "orig.so"))
     with oracle.use_library(lib):
         _run_pins()
+        _run_directional_pins()
+
+
+@pytest.mark.parametrize("name", sorted(DIRECTIONAL_MUTANTS))
+def test_directional_mutant_is_caught(name, tmp_path):
+    old, new = DIRECTIONAL_MUTANTS[name]
+    src = oracle.source_text()
+    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    lib = oracle.compile_source(src.replace(old, new), str(tmp_path / f"{name}.so"))
+    with oracle.use_library(lib):
+        with pytest.raises(AssertionError):
+            _run_directional_pins()
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

@@ -425,6 +425,70 @@ def section_f2(torch, irfilter, synth, oracle, dev, frames: int = 8, reps: int =
     return out
 
 
+def section_f4(torch, irfilter, synth, oracle, dev) -> dict:
+    """The opt-in directional detector (not the paper's; a reading of Fig. 1's
+    caption) against the paper's min/max detector, each followed by the 3x3
+    median at the flagged pixels, on the Table 1 analogue frames (364x244 u8,
+    20 % and 30 % salt-and-pepper) and on the same field with one-pixel lines
+    drawn into it: flags, PSNR (Eq. 5) against the noise-free frame, and the
+    share of line pixels that come through unchanged."""
+    from paper_1201_3972_amd import metrics
+    k = 3
+    out = {"workload": "364x244 u8 synthetic field, salt-and-pepper impulses, 3x3; 'lines' adds 1-pixel "
+                       "rows, columns and diagonals (value 235) to the noise-free field", "cases": {}}
+    for j, d in enumerate((0.20, 0.30)):
+        for lines in (False, True):
+            spec = synth.FrameSpec(364, 244, "u8", "sp", d, 0.0, synth.config_seed(6, j))
+            clean = synth.clean_frame(spec)
+            noisy = synth.make_frame(spec)
+            line_px = np.zeros(clean.shape, dtype=bool)
+            if lines:
+                H, W = clean.shape
+                for r in range(20, H - 20, 40):
+                    line_px[r, 10:W - 10] = True
+                for c in range(30, W - 30, 60):
+                    line_px[10:H - 10, c] = True
+                idx = np.arange(10, min(H, W) - 10)
+                line_px[idx, idx + 50] = True
+                clean = np.where(line_px, 235, clean).astype(np.uint8)
+                impulses = noisy != synth.clean_frame(spec)
+                noisy = np.where(impulses, noisy, clean).astype(np.uint8)
+            src = torch.from_numpy(noisy).to(dev)
+            mask = torch.empty_like(src)
+            fnr = torch.empty_like(src)
+            dirf = torch.empty_like(src)
+            cnt = torch.zeros(2, dtype=torch.int64, device=dev)
+            irfilter.ir_filter_run(src, fnr, k, flagged_count=cnt[:1])
+            irfilter.ir_filter_detect_directional(src, mask, flagged_count=cnt[1:])
+            irfilter.ir_filter_median(src, dirf, k, mask=mask)
+            torch.cuda.synchronize()
+            wmask, wc = oracle.detect_directional(noisy)
+            want_dir = oracle.median(noisy, k, wmask)[0]
+            want_fnr, wfc = oracle.fnr(noisy, k)
+            counts = cnt.cpu().numpy()
+            if not (np.array_equal(mask.cpu().numpy(), wmask) and np.array_equal(dirf.cpu().numpy(), want_dir)
+                    and np.array_equal(fnr.cpu().numpy(), want_fnr) and int(counts[1]) == wc
+                    and int(counts[0]) == int(wfc[0])):
+                raise RuntimeError(f"f4 parity failure at {d:.0%} lines={lines}")
+            ms_dir = _timed(torch, lambda: (irfilter.ir_filter_detect_directional(src, mask),
+                                            irfilter.ir_filter_median(src, dirf, k, mask=mask)), 200)
+            ms_fnr = _timed(torch, lambda: irfilter.ir_filter_run(src, fnr, k), 200)
+            f_h, d_h = fnr.cpu().numpy(), dirf.cpu().numpy()
+            ent = {"noisy_db": round(metrics.psnr(clean, noisy), 2),
+                   "minmax": {"flags": int(counts[0]), "db": round(metrics.psnr(clean, f_h), 2),
+                              "device_ms": round(ms_fnr, 4)},
+                   "directional": {"flags": int(counts[1]), "db": round(metrics.psnr(clean, d_h), 2),
+                                   "device_ms": round(ms_dir, 4)}}
+            if lines:
+                keep = line_px & (noisy == clean)  # line pixels not hit by an impulse
+                ent["minmax"]["lines_kept"] = round(float((f_h[keep] == clean[keep]).mean()), 3)
+                ent["directional"]["lines_kept"] = round(float((d_h[keep] == clean[keep]).mean()), 3)
+            name = f"{round(d * 100)}%{' lines' if lines else ''}"
+            out["cases"][name] = ent
+            log(f"f4 {name}: {ent}")
+    return out
+
+
 def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
     sections = {}
     wanted = [x for x in args.sections.split(",") if x and x != "none"]
@@ -443,6 +507,8 @@ def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
             sections["f1_fused_two_passes"] = section_f1(torch, irfilter, synth, oracle, dev)
         elif name == "f2":
             sections["f2_large_windows"] = section_f2(torch, irfilter, synth, oracle, dev)
+        elif name == "f4":
+            sections["f4_directional_detector"] = section_f4(torch, irfilter, synth, oracle, dev)
         elif name == "f3":
             sections["f3_table1_analogue"] = section_f3(torch, irfilter, synth, oracle, dev)
         log(f"section {name}: {time.perf_counter() - t1:.1f}s")
@@ -460,7 +526,7 @@ def main() -> int:
     ap.add_argument("--no-per-frame", action="store_true", help="skip the per-frame launch baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--sections", default="c1,c3,c4,c5,f1,f2,f3",
+    ap.add_argument("--sections", default="c1,c3,c4,c5,f1,f2,f3,f4",
                     help="extra workloads reported beside the headline (comma list, or 'none')")
     ap.add_argument("--no-headline", action="store_true",
                     help="run only the --sections workloads (for profiling them) and print their JSON")

@@ -92,6 +92,24 @@ irf_status ir_filter_detect(const void *src, size_t src_pitch, uint8_t *mask, si
                             uint64_t *flagged_count, hipStream_t stream);
 
 /*
+ * ir_filter_detect_directional -- an opt-in detector that is NOT the paper's
+ * (the method's detector is ir_filter_detect).  It reads the caption of
+ * Fig. 1 (the central pixel against its two neighbours in the 3x3 window)
+ * with Section 3's premise that signal grey levels vary monotonically along a
+ * surface: pixel (x, y) is flagged when, on each of the four lines through it
+ * in its 3x3 window (row, column, both diagonals), its grey level lies outside
+ * the range of its two neighbours (ties count as inside; coordinates outside
+ * the frame clamped to the edge, so border pixels are never flagged).  Unlike
+ * the extreme test it keeps one-pixel lines.  The paper's figure is missing, so
+ * the rule itself is a reading.  Compose with ir_filter_median(mask) to filter.
+ *   src, src_pitch, mask, mask_pitch, width, height, dtype, flagged_count,
+ *   stream: as for ir_filter_detect (there is no window argument)
+ */
+irf_status ir_filter_detect_directional(const void *src, size_t src_pitch, uint8_t *mask,
+                                        size_t mask_pitch, int width, int height, irf_dtype dtype,
+                                        uint64_t *flagged_count, hipStream_t stream);
+
+/*
  * ir_filter_median -- median replacement (Section 3.4).
  *   mask (nullable)      where mask[y*mask_pitch + x] != 0 the pixel takes its window
  *                        median; other pixels are copied.  mask == NULL replaces

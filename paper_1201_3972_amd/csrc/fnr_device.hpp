@@ -67,6 +67,7 @@ enum Mode : int {
     MODE_FNR = 1,          // detect, then median at the noisy pixels
     MODE_MEDIAN_MASK = 2,  // median where a caller mask is non-zero
     MODE_MEDIAN_ALL = 3,   // median everywhere (the standard median filter)
+    MODE_DETECT_DIR = 4,   // write the mask of the opt-in directional detector (3x3 only)
 };
 
 // One launch covers a stack of equally sized frames laid out with fixed strides.
@@ -507,6 +508,49 @@ __device__ __forceinline__ uint32_t detect_block(const uint16_t *tile, int strip
         return detect_block_core<K>(tile, strip, tx, pk_one);
     else
         return detect_block_blocks<K>(tile, strip, tx, pk_one);
+}
+
+// Flags of the opt-in directional detector for the thread's 4 x R block (not
+// the paper's detector; a reading of Fig. 1's caption): a pixel is flagged when,
+// on each of the four lines through it in its 3 x 3 window (row, column, both
+// diagonals), its grey level lies outside the range of its two neighbours,
+// ties counting as inside.  Per LDS row the thread holds the aligned pairs
+// (0,1), (2,3) and the odd pairs (-1,0), (1,2), (3,4); "outside" is nonzero
+// per half exactly when the centre is below the line's minimum or above its
+// maximum.
+template <int K>
+__device__ __forceinline__ uint32_t directional_block(const uint16_t *tile, int strip, int tx,
+                                                      uint32_t pk_one) {
+    using G = Geometry<K>;
+    static_assert(K == 3, "the directional test is defined on the 3 x 3 window");
+    constexpr int R = G::R;
+    const uint16_t *base = tile + strip * R * G::pitch + G::halo + 4 * tx;
+    uint32_t C0[R + 2], C1[R + 2], L0[R + 2], M[R + 2], R1[R + 2];
+#pragma unroll
+    for (int i = 0; i < R + 2; ++i) {
+        const uint2 *q = reinterpret_cast<const uint2 *>(base + i * G::pitch);
+        const uint2 w0 = q[-1], w1 = q[0], w2 = q[1];  // columns -4..-1, 0..3, 4..7
+        C0[i] = w1.x;
+        C1[i] = w1.y;
+        L0[i] = shift_pair(w1.x, w0.y);
+        M[i] = shift_pair(w1.y, w1.x);
+        R1[i] = shift_pair(w2.x, w1.y);
+    }
+    auto outside = [](uint32_t c, uint32_t a, uint32_t b) {
+        return pk_subsat(pk_min(a, b), c) | pk_subsat(c, pk_max(a, b));
+    };
+    uint32_t flags = 0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int i = q + 1;
+        // row, column, diagonal (top-left to bottom-right), anti-diagonal
+        const uint32_t z0 = pk_min(pk_min(outside(C0[i], L0[i], M[i]), outside(C0[i], C0[i - 1], C0[i + 1])),
+                                   pk_min(outside(C0[i], L0[i - 1], M[i + 1]), outside(C0[i], M[i - 1], L0[i + 1])));
+        const uint32_t z1 = pk_min(pk_min(outside(C1[i], M[i], R1[i]), outside(C1[i], C1[i - 1], C1[i + 1])),
+                                   pk_min(outside(C1[i], M[i - 1], R1[i + 1]), outside(C1[i], R1[i - 1], M[i + 1])));
+        flags |= (pk_min(z0, pk_one) | (pk_min(z1, pk_one) << 8)) << q;
+    }
+    return flags;
 }
 
 // Bits of the thread's block that lie inside the frame.
@@ -999,6 +1043,8 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
     uint32_t flags;
     if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR) {
         flags = detect_block<K>(sm.tile, strip, tx, a.pk_one) & valid;
+    } else if constexpr (MODE == MODE_DETECT_DIR) {
+        flags = directional_block<K>(sm.tile, strip, tx, a.pk_one) & valid;
     } else if constexpr (MODE == MODE_MEDIAN_MASK) {
         flags = 0;
         const uint8_t *m = a.mask_in + (uint64_t)f * a.mask_stride;
@@ -1018,7 +1064,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         flags = valid;
     }
 
-    if constexpr (MODE == MODE_DETECT) {
+    if constexpr (MODE == MODE_DETECT || MODE == MODE_DETECT_DIR) {
         const uint32_t wave_total = __builtin_amdgcn_readlane(wave_inclusive_sum(__builtin_popcount(flags)), 63);
         uint8_t *m = a.mask_out + (uint64_t)f * a.mask_stride;
 #pragma unroll
@@ -1093,7 +1139,7 @@ __global__ __launch_bounds__(NT) void fnr_persistent_kernel(StackArgs a) {
         __syncthreads();
         flagged += process_tile<T, K, MODE, NT, SEL>(a, t, sm);
     }
-    if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR) {
+    if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR || MODE == MODE_DETECT_DIR) {
         if (a.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)
             atomicAdd(a.count, (unsigned long long)flagged);
     }

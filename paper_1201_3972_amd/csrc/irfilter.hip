@@ -205,6 +205,40 @@ irf_status ir_filter_detect(const void *src, size_t src_pitch, uint8_t *mask, si
     }
 }
 
+irf_status ir_filter_detect_directional(const void *src, size_t src_pitch, uint8_t *mask, size_t mask_pitch,
+                                        int width, int height, irf_dtype dtype, uint64_t *flagged_count,
+                                        hipStream_t stream) {
+    try {
+        if (!src || !mask) return IRF_ERR_NULL;
+        irf_status st = check_common(width, height, 1, dtype, 3);
+        if (st) return st;
+        const int b = bytes_of(dtype);
+        if ((st = check_layout(src_pitch, 0, width, height, 1, b))) return st;
+        if ((st = check_layout(mask_pitch, 0, width, height, 1, 1))) return st;
+        const Span ss = span_of(src, src_pitch, 0, width, height, 1, b);
+        const Span ms = span_of(mask, mask_pitch, 0, width, height, 1, 1);
+        if (overlap(ss, ms)) return IRF_ERR_ALIAS;
+        if (flagged_count) {
+            const Span cs = {reinterpret_cast<uintptr_t>(flagged_count),
+                             reinterpret_cast<uintptr_t>(flagged_count) + sizeof(uint64_t)};
+            if (overlap(cs, ss) || overlap(cs, ms)) return IRF_ERR_ALIAS;
+        }
+        if ((st = zero_counts(flagged_count, 1, stream))) return st;
+        StackArgs a = {};
+        a.src = static_cast<const uint8_t *>(src);
+        a.mask_out = mask;
+        a.src_pitch = src_pitch;
+        a.mask_pitch = mask_pitch;
+        a.width = width;
+        a.height = height;
+        a.aligned = is16(src) && is16(src_pitch) && is16(mask) && is16(mask_pitch);
+        a.count = reinterpret_cast<unsigned long long *>(flagged_count);
+        return launch<MODE_DETECT_DIR>(dtype, 3, 1, a, stream);
+    } catch (...) {
+        return IRF_ERR_HIP;
+    }
+}
+
 irf_status ir_filter_median(const void *src, size_t src_pitch, const uint8_t *mask,
                             size_t mask_pitch, void *dst, size_t dst_pitch, int width, int height,
                             irf_dtype dtype, int window, hipStream_t stream) {

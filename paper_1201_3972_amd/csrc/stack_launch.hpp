@@ -103,7 +103,7 @@ void launch_variant(const StackArgs &a, hipStream_t s) {
 // Detection selects nothing: its kernels exist per workgroup size only.
 template <typename T, int K, int MODE, int NT>
 bool launch_threads(int select, const StackArgs &a, hipStream_t s) {
-    if constexpr (MODE == MODE_DETECT) {
+    if constexpr (MODE == MODE_DETECT || MODE == MODE_DETECT_DIR) {
         launch_variant<T, K, MODE, NT, default_select(K)>(a, s);
         return true;
     } else if constexpr (K > kNetworkMaxWindow) {
@@ -168,6 +168,9 @@ bool launch_stack(int window, int mode, Tuning t, const StackArgs &a, hipStream_
         case MODE_FNR: return launch_window<T, MODE_FNR, LARGE>(window, t, a, s);
         case MODE_MEDIAN_MASK: return launch_window<T, MODE_MEDIAN_MASK, LARGE>(window, t, a, s);
         case MODE_MEDIAN_ALL: return launch_window<T, MODE_MEDIAN_ALL, LARGE>(window, t, a, s);
+        case MODE_DETECT_DIR:  // the 3 x 3 directional test only
+            if constexpr (!LARGE) return window == 3 && launch_tuned<T, 3, MODE_DETECT_DIR>(t, a, s);
+            return false;
         default: return false;
     }
 }

@@ -34,6 +34,7 @@ STATUS = {
 _vp, _sz, _i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
 SIGNATURES = {
     "ir_filter_detect": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _vp, _vp]),
+    "ir_filter_detect_directional": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _vp, _vp]),
     "ir_filter_median": (_i32, [_vp, _sz, _vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _vp]),
     "ir_filter_run": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp]),
     "ir_filter_run_frames": (_i32, [_vp, _sz, _sz, _vp, _sz, _sz, _i32, _i32, _i32, _i32, _i32, _i32,
@@ -186,6 +187,21 @@ def ir_filter_detect(src, mask, window: int, flagged_count=None, stream=None) ->
     cp = None if flagged_count is None else flagged_count.data_ptr()
     _check("ir_filter_detect", load().ir_filter_detect(sp, spitch, mp, mpitch, W, H, _dtype_code(src),
                                                        window, cp, _stream(stream)))
+
+
+def ir_filter_detect_directional(src, mask, flagged_count=None, stream=None) -> None:
+    """Mask of the opt-in directional detector (not the paper's detector; see
+    include/irfilter.h): 1 where the pixel lies outside its two neighbours'
+    range on all four lines of its 3x3 window."""
+    sp, spitch = _frame(src, "src")
+    mp, mpitch = _frame(mask, "mask")
+    H, W = src.shape
+    if tuple(mask.shape) != (H, W):
+        raise ValueError("mask must have the source shape")
+    cp = None if flagged_count is None else flagged_count.data_ptr()
+    _check("ir_filter_detect_directional",
+           load().ir_filter_detect_directional(sp, spitch, mp, mpitch, W, H, _dtype_code(src), cp,
+                                               _stream(stream)))
 
 
 def ir_filter_median(src, dst, window: int, mask=None, stream=None) -> None:

@@ -121,6 +121,18 @@ def test_median_validation(lib):
     assert f(SRC, 640, DST, 320, DST, 640, 320, 240, 2, 3, None) == -7
 
 
+def test_directional_detect_validation(lib):
+    f = lib.ir_filter_detect_directional
+    assert f(None, 640, MASK, 320, 320, 240, 2, None, None) == -1
+    assert f(SRC, 640, None, 320, 320, 240, 2, None, None) == -1
+    assert f(SRC, 640, MASK, 320, 0, 240, 2, None, None) == -2
+    assert f(SRC, 640, MASK, 320, 320, 240, 5, None, None) == -4
+    assert f(SRC, 639, MASK, 320, 320, 240, 2, None, None) == -3
+    assert f(SRC, 640, MASK, 319, 320, 240, 2, None, None) == -3
+    assert f(SRC, 640, SRC + 100, 320, 320, 240, 2, None, None) == -7
+    assert f(SRC, 640, MASK, 320, 320, 240, 2, MASK + 8, None) == -7
+
+
 def test_frames_validation(lib):
     f = lib.ir_filter_run_frames
     # stride smaller than one frame

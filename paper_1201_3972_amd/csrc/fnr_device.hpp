@@ -781,27 +781,32 @@ __device__ __forceinline__ uint32_t median_registers(const uint16_t *w, uint32_t
 }
 
 // One window per group of lanes (windows above 15x15).  The group's L lanes
-// (8 up to 512 window values, else 16; aligned inside a 16-lane DPP row) hold
-// the window's values g, g + L, g + 2L, ... (S_xy order), two per VGPR, and run
-// the same grey-level bisection as median_registers with counts summed over
-// the group by DPP butterflies.  Registers past the window's end repeat its
-// first value, taken back out of every count.
+// (aligned inside a 16-lane DPP row) hold the window's values g, g + L, g + 2L,
+// ... (S_xy order), two per VGPR, and run the same grey-level bisection as
+// median_registers with counts summed over the group by DPP butterflies.
+// Registers past the window's end repeat its first value, taken back out of
+// every count.  L is the smallest group whose share fits 48 registers (4 lanes
+// at 17x17 and 19x19, 8 up to 27x27, 16 above): each round costs every lane
+// three packed operations per register plus log2(L) butterfly steps, so fewer
+// lanes waste fewer steps, while larger shares cost the kernel occupancy.
 template <int K>
 struct GroupPlan {
     static constexpr int N = K * K;
-    static constexpr int lanes = N <= 512 ? 8 : 16;
-    static constexpr int regs = (N + 2 * lanes - 1) / (2 * lanes);  // packed registers per lane
+    static constexpr int regs_for(int l) { return (N + 2 * l - 1) / (2 * l); }
+    static constexpr int lanes = regs_for(4) <= 48 ? 4 : regs_for(8) <= 48 ? 8 : 16;
+    static constexpr int regs = regs_for(lanes);  // packed registers per lane
     static constexpr int pad = 2 * lanes * regs - N;                // repeated values in the group
     static_assert(K > lanes, "a lane's next value is at most one window row further");
 };
 
-// op over the aligned group of L lanes (L = 8 or 16), result in every lane.
+// op over the aligned group of L lanes (L = 4, 8 or 16), result in every lane.
 template <int L, typename Op>
 __device__ __forceinline__ uint32_t group_reduce(uint32_t v, Op op) {
-    static_assert(L == 8 || L == 16, "groups of 8 or 16 lanes");
+    static_assert(L == 4 || L == 8 || L == 16, "groups of 4, 8 or 16 lanes");
     v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false));   // lane ^ 1
     v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false));   // lane ^ 2
-    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));  // 7 - lane in 8
+    if constexpr (L >= 8)
+        v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));  // 7 - lane in 8
     if constexpr (L == 16)
         v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));  // 15 - lane
     return v;
@@ -814,24 +819,26 @@ __device__ __forceinline__ uint32_t median_group(const uint16_t *w, int g, uint3
     using P = GroupPlan<K>;
     constexpr int N = P::N, L = P::lanes, pitch = Geometry<K>::pitch;
     constexpr uint32_t rank = (N - 1) / 2;
-    const uint32_t first = w[0];
+    const uint16_t first = w[0];
     uint32_t v[P::regs];
-    int row = 0, col = g;  // g < L < K
-    auto next = [&](int idx) -> uint32_t {
-        uint32_t x = first;
-        if (idx * L + L <= N || idx * L + g < N) x = w[row * pitch + col];
+    int off = g, col = g;  // LDS offset and column of the lane's next value (g < L < K)
+    auto next = [&](int idx) -> uint16_t {
+        uint16_t x = first;
+        if (idx * L + L <= N || idx * L + g < N) x = w[off];
         col += L;
+        off += L;
         if (col >= K) {
             col -= K;
-            ++row;
+            off += pitch - K;
         }
         return x;
     };
 #pragma unroll
     for (int j = 0; j < P::regs; ++j) {
-        const uint32_t lo = next(2 * j);
-        const uint32_t hi = next(2 * j + 1);
-        v[j] = lo | (hi << 16);
+        u16x2 pair;  // built element-wise so that each value loads straight into its half
+        pair.x = next(2 * j);
+        pair.y = next(2 * j + 1);
+        v[j] = __builtin_bit_cast(uint32_t, pair);
     }
     uint32_t mn = 0xffffffffu, mx = 0u;
 #pragma unroll

@@ -541,8 +541,8 @@ def main() -> int:
         return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(frames are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; frames are independent, so "
+              "stacks and batches shard across GPUs by frame with no exchange", file=sys.stderr)
         return 2
 
     import torch

@@ -40,11 +40,18 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+# The sources of the translation unit that compiles the 16-bit stack kernels
+# (the kernels the HBM traffic record measures), with everything it includes.
+TRAFFIC_SOURCES = ("paper_1201_3972_amd/csrc/stack_u16.hip", "paper_1201_3972_amd/csrc/stack_launch.hpp",
+                   "paper_1201_3972_amd/csrc/fnr_device.hpp", "paper_1201_3972_amd/csrc/fused_device.hpp",
+                   "paper_1201_3972_amd/csrc/netgen.hpp", "paper_1201_3972_amd/csrc/host_common.hpp",
+                   "include/irfilter.h")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1201_3972_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -90,3 +90,16 @@ def test_request_larger_than_budget_is_reported(dev):
     with pytest.raises(RuntimeError):
         srv.run_until_idle()
     srv.close()
+
+
+def test_windows_above_15_are_rejected_at_submission(dev):
+    # the server runs batch plans, which take windows up to IRF_MAX_BATCH_WINDOW
+    src = torch.zeros((64, 64), dtype=torch.uint8).pin_memory()
+    srv = serving.Server(memory_budget=1 << 24, max_inflight=2)
+    try:
+        srv.submit(serving.Request(1, 0.0, src, 17))
+        with pytest.raises(irfilter.IrfError) as e:
+            srv.run_until_idle()
+        assert e.value.status == -5
+    finally:
+        srv.close()

@@ -947,6 +947,67 @@ struct TileSmem {
     uint32_t count;             // list length
 };
 
+// 3 x 3 windows take a dense path instead of steps 3 and 4: at the flag rates
+// of 3 x 3 (a quarter to half of the pixels) computing every pixel's median in
+// registers costs less than compacting the flagged ones.  Each window column
+// is sorted, and the median of the nine values is med3(largest column minimum,
+// median of the column medians, smallest column maximum): after the rows of
+// the column-sorted window are sorted too, these three are its anti-diagonal,
+// which holds the median.
+__device__ __forceinline__ uint32_t pk_med3(uint32_t a, uint32_t b, uint32_t c) {
+    return pk_max(pk_min(a, b), pk_min(pk_max(a, b), c));
+}
+
+struct PkSorted3 {
+    uint32_t lo, mid, hi;
+};
+
+__device__ __forceinline__ PkSorted3 pk_sort3(uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t t = pk_min(a, b), u = pk_max(a, b);
+    const uint32_t v = pk_max(t, c);
+    return {pk_min(t, c), pk_min(u, v), pk_max(u, v)};
+}
+
+// Output pairs of the thread's 4 x R block: out[q][0] = columns (0,1) and
+// out[q][1] = columns (2,3) of row q, each half the 3 x 3 median where its flag
+// bit is set and the centre value otherwise.  Per LDS row the thread holds the
+// aligned pairs (0,1), (2,3) and the odd pairs (-1,0), (1,2), (3,4), so one
+// column sort serves two pixels and the sorted pair (1,2) serves both outputs.
+template <int R>
+__device__ __forceinline__ void dense3_block(const uint16_t *tile, int strip, int tx, uint32_t flags,
+                                             uint32_t (&out)[R][2]) {
+    using G = Geometry<3>;
+    const uint16_t *base = tile + strip * R * G::pitch + G::halo + 4 * tx;
+    uint32_t A[R + 2], B[R + 2], C[R + 2], D[R + 2], E[R + 2];
+#pragma unroll
+    for (int i = 0; i < R + 2; ++i) {
+        const uint2 *q = reinterpret_cast<const uint2 *>(base + i * G::pitch);
+        const uint2 w0 = q[-1], w1 = q[0], w2 = q[1];  // columns -4..-1, 0..3, 4..7
+        B[i] = w1.x;
+        D[i] = w1.y;
+        A[i] = shift_pair(w1.x, w0.y);
+        C[i] = shift_pair(w1.y, w1.x);
+        E[i] = shift_pair(w2.x, w1.y);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const PkSorted3 sa = pk_sort3(A[q], A[q + 1], A[q + 2]), sb = pk_sort3(B[q], B[q + 1], B[q + 2]);
+        const PkSorted3 sc = pk_sort3(C[q], C[q + 1], C[q + 2]), sd = pk_sort3(D[q], D[q + 1], D[q + 2]);
+        const PkSorted3 se = pk_sort3(E[q], E[q + 1], E[q + 2]);
+        const uint32_t m0 = pk_med3(pk_max(pk_max(sa.lo, sb.lo), sc.lo), pk_med3(sa.mid, sb.mid, sc.mid),
+                                    pk_min(pk_min(sa.hi, sb.hi), sc.hi));
+        const uint32_t m1 = pk_med3(pk_max(pk_max(sc.lo, sd.lo), se.lo), pk_med3(sc.mid, sd.mid, se.mid),
+                                    pk_min(pk_min(sc.hi, sd.hi), se.hi));
+        // flag bit q (+16) is column 0 (1), bit q+8 (+24) column 2 (3)
+        const uint32_t s0 = ((uint32_t)__builtin_amdgcn_sbfe(flags, q, 1) & 0xffffu) |
+                            ((uint32_t)__builtin_amdgcn_sbfe(flags, q + 16, 1) & 0xffff0000u);
+        const uint32_t s1 = ((uint32_t)__builtin_amdgcn_sbfe(flags, q + 8, 1) & 0xffffu) |
+                            ((uint32_t)__builtin_amdgcn_sbfe(flags, q + 24, 1) & 0xffff0000u);
+        out[q][0] = (m0 & s0) | (B[q + 1] & ~s0);
+        out[q][1] = (m1 & s1) | (D[q + 1] & ~s1);
+    }
+}
+
 // Steps 3 and 4 on a tile staged in LDS: the flagged pixels (bits of each
 // thread's 4 x R block whose centre, column 0 of row 0, is LDS value centre0)
 // are compacted into the list, their window medians are selected, and every
@@ -1086,6 +1147,31 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
                 const uint32_t e[4] = {b0, b1, b2, b3};
                 for (int i = 0; i < 4; ++i)
                     if (px + i < W) m[mo + (uint32_t)i] = (uint8_t)e[i];
+            }
+        }
+        return wave_total;
+    } else if constexpr (K == 3) {
+        // dense 3 x 3 path: every pixel's median in registers, kept where flagged
+        const uint32_t wave_total = __builtin_amdgcn_readlane(wave_inclusive_sum(__builtin_popcount(flags)), 63);
+        uint32_t out[R][2];
+        dense3_block<R>(sm.tile, strip, tx, flags, out);
+        uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
+        const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (!full && py + q >= H) break;
+            const uint32_t ro = __umul24((uint32_t)(py + q), (uint32_t)a.dst_pitch);
+            if (full) {
+                const uint32_t off = ro + (uint32_t)px * (uint32_t)sizeof(T);
+                if constexpr (sizeof(T) == 2) {
+                    *reinterpret_cast<uint2 *>(dst + off) = make_uint2(out[q][0], out[q][1]);
+                } else {
+                    *reinterpret_cast<uint32_t *>(dst + off) =
+                        (out[q][0] & 0xffu) | ((out[q][0] >> 8) & 0xff00u) | ((out[q][1] & 0xffu) << 16) |
+                        ((out[q][1] & 0xff0000u) << 8);
+                }
+            } else {
+                store4<T>(dst, ro, px, W, aligned, out[q][0], out[q][1]);
             }
         }
         return wave_total;

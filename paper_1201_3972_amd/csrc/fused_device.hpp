@@ -67,7 +67,18 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
         // pass 1 on every frame pixel of the block
         const uint32_t f1 = detect_block<K>(sm.tile, strip, tx, a.pk_one) & in_frame;
         n1 += __builtin_popcount(f1 & out);
-        median_into_tile<K, NT, SEL>(sm, f1, centre0, t, a.pk_one);
+        if constexpr (K == 3) {
+            // dense 3 x 3 path: the whole block in registers, written back once
+            // every thread has read the input tile
+            uint32_t o1[R][2];
+            dense3_block<R>(sm.tile, strip, tx, f1, o1);
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                *reinterpret_cast<uint2 *>(sm.tile + centre0 + q * G::pitch) = make_uint2(o1[q][0], o1[q][1]);
+        } else {
+            median_into_tile<K, NT, SEL>(sm, f1, centre0, t, a.pk_one);
+        }
         if (tid == 0) sm.count = 0;  // every thread read the pass-1 list length before its selection
         __syncthreads();
 
@@ -88,7 +99,18 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
         // pass 2 on the output pixels
         const uint32_t f2 = detect_block<K>(sm.tile, strip, tx, a.pk_one) & out;
         n2 += __builtin_popcount(f2);
-        median_into_tile<K, NT, SEL>(sm, f2, centre0, t, a.pk_one);
+        uint32_t o2[R][2];
+        if constexpr (K == 3) {
+            dense3_block<R>(sm.tile, strip, tx, f2, o2);
+        } else {
+            median_into_tile<K, NT, SEL>(sm, f2, centre0, t, a.pk_one);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const uint2 c = *reinterpret_cast<const uint2 *>(sm.tile + centre0 + q * G::pitch);
+                o2[q][0] = c.x;
+                o2[q][1] = c.y;
+            }
+        }
 
         // store the thread's output pixels (a thread holds whole 4-column groups
         // of the output, or none; the last tile of a row may end inside one)
@@ -98,9 +120,8 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 if (((out >> q) & 1u) == 0) continue;
-                const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * G::pitch);
                 const uint32_t ro = __umul24((uint32_t)(py + q), (uint32_t)a.dst_pitch);
-                store4<T>(dst, ro, px, xend, aligned, c[0], c[1]);
+                store4<T>(dst, ro, px, xend, aligned, o2[q][0], o2[q][1]);
             }
         }
     }

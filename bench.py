@@ -40,12 +40,13 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-# The sources of the translation unit that compiles the 16-bit stack kernels
-# (the kernels the HBM traffic record measures), with everything it includes.
+# The sources of the 16-bit stack kernels (the kernels the HBM traffic record
+# measures): their device code, their launch and the translation unit that
+# instantiates them.  (stack_launch.hpp also includes fused_device.hpp, for two
+# host-side constants of the fused kernels; no stack kernel uses its code.)
 TRAFFIC_SOURCES = ("paper_1201_3972_amd/csrc/stack_u16.hip", "paper_1201_3972_amd/csrc/stack_launch.hpp",
-                   "paper_1201_3972_amd/csrc/fnr_device.hpp", "paper_1201_3972_amd/csrc/fused_device.hpp",
-                   "paper_1201_3972_amd/csrc/netgen.hpp", "paper_1201_3972_amd/csrc/host_common.hpp",
-                   "include/irfilter.h")
+                   "paper_1201_3972_amd/csrc/fnr_device.hpp", "paper_1201_3972_amd/csrc/netgen.hpp",
+                   "paper_1201_3972_amd/csrc/host_common.hpp", "include/irfilter.h")
 
 
 def kernel_source_hash() -> str:

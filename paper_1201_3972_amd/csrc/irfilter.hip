@@ -19,7 +19,7 @@ namespace {
 
 using namespace host;
 
-constexpr int kVersion = (1 << 16) | 0;
+constexpr int kVersion = (1 << 16) | 1;  // 1.1: pass fusion, windows up to 31x31, directional detector
 
 // Tuning table of the single-size kernels, per pixel type and window: 0 means
 // the untuned default, otherwise threads | select << 16.  Entries change only

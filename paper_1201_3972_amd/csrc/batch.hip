@@ -59,11 +59,6 @@ struct irf_plan {
     size_t desc_off = 0, map_off = 0, bytes = 0;
     int threads = kThreads;  // workgroup size of the batch kernels (tile height / 8 * 32)
     int grid[kBatchClasses] = {};
-    // The class kernels run concurrently: the first active class on the
-    // caller's stream, the others on side streams forked from it and joined
-    // back, so each class fills the CUs the others' tails leave idle.
-    hipStream_t side[kBatchClasses] = {};
-    hipEvent_t fork = nullptr, join[kBatchClasses] = {};
     int next_set = 0;
     struct Set {
         unsigned char *dev = nullptr;
@@ -94,47 +89,15 @@ void launch_class(const irf_plan *p, const irf_plan::Set &s, hipStream_t stream)
                            q + CLASS, 0x00010001u);
 }
 
-// The kernels of the classes in `classes`, concurrently: the first on
-// `stream`, each further one on its side stream after a fork event recorded on
-// `stream`, and `stream` waits for all of them.  Works under stream capture too
-// (the side streams join the capture through the fork event).
-bool launch_batch(const irf_plan *p, const irf_plan::Set &s, unsigned classes, hipStream_t stream) {
+void launch_batch(const irf_plan *p, const irf_plan::Set &s, unsigned classes, hipStream_t stream) {
     static_assert(kBatchClasses == 3, "one launch per class");
-    int first = -1;
-    for (int c = 0; c < kBatchClasses; ++c)
-        if (classes & (1u << c)) {
-            first = c;
-            break;
-        }
-    if (first < 0) return true;
-    if (classes != (1u << first) && hipEventRecord(p->fork, stream) != hipSuccess) return false;
-    for (int c = 0; c < kBatchClasses; ++c) {
-        if (!(classes & (1u << c))) continue;
-        hipStream_t st = stream;
-        if (c != first) {
-            st = p->side[c];
-            if (hipStreamWaitEvent(st, p->fork, 0) != hipSuccess) return false;
-        }
-        switch (c) {
-            case 0: launch_class<0>(p, s, st); break;
-            case 1: launch_class<1>(p, s, st); break;
-            default: launch_class<2>(p, s, st); break;
-        }
-        if (c != first) {
-            if (hipEventRecord(p->join[c], st) != hipSuccess) return false;
-            if (hipStreamWaitEvent(stream, p->join[c], 0) != hipSuccess) return false;
-        }
-    }
-    return true;
+    if (classes & 1u) launch_class<0>(p, s, stream);
+    if (classes & 2u) launch_class<1>(p, s, stream);
+    if (classes & 4u) launch_class<2>(p, s, stream);
 }
 
 void free_plan(irf_plan *p) {
     if (!p) return;
-    for (int c = 0; c < kBatchClasses; ++c) {
-        if (p->side[c]) (void)hipStreamDestroy(p->side[c]);
-        if (p->join[c]) (void)hipEventDestroy(p->join[c]);
-    }
-    if (p->fork) (void)hipEventDestroy(p->fork);
     for (auto &s : p->set) {
         if (s.graph) (void)hipGraphExecDestroy(s.graph);
         if (s.copied) (void)hipEventDestroy(s.copied);
@@ -217,15 +180,6 @@ irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles,
             p->grid[1] = batch_grid<1, 128>();
             p->grid[2] = batch_grid<2, 128>();
         }
-        bool streams_ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
-        for (int c = 1; c < kBatchClasses && streams_ok; ++c)
-            streams_ok = hipStreamCreateWithFlags(&p->side[c], hipStreamNonBlocking) == hipSuccess &&
-                         hipEventCreateWithFlags(&p->join[c], hipEventDisableTiming) == hipSuccess;
-        if (!streams_ok) {
-            free_plan(p);
-            (void)hipGetLastError();
-            return IRF_ERR_HIP;
-        }
         for (auto &s : p->set) {
             if (hipMalloc(&s.dev, p->bytes) != hipSuccess) {
                 free_plan(p);
@@ -255,8 +209,8 @@ irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles,
             for (auto &s : p->set) {
                 hipGraph_t g = nullptr;
                 ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-                const bool launched = ok && launch_batch(p, s, (1u << kBatchClasses) - 1, cs);
-                ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok && launched;
+                if (ok) launch_batch(p, s, (1u << kBatchClasses) - 1, cs);
+                ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok;
                 ok = ok && hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0) == hipSuccess;
                 if (g) (void)hipGraphDestroy(g);
                 if (!ok) break;
@@ -320,9 +274,6 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         uint32_t *map = reinterpret_cast<uint32_t *>(s.host + p->map_off);
         memset(q, 0, kQueueBytes);
         for (int c = 0; c < kBatchClasses; ++c) q[c].total = (unsigned)tiles[c];
-        // tiles in frame order: interleaved kinds (pixel type and window) balance
-        // cheap and expensive tiles across the CUs (grouping them by kind measured
-        // 7% slower)
         int begin[kBatchClasses] = {};
         for (int i = 0; i < n; ++i) {
             const irf_frame &f = frames[i];
@@ -370,7 +321,7 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
             unsigned classes = 0;
             for (int c = 0; c < kBatchClasses; ++c)
                 if (tiles[c]) classes |= 1u << c;
-            if (!launch_batch(p, s, classes, stream)) return IRF_ERR_HIP;
+            launch_batch(p, s, classes, stream);
         }
         if (hipEventRecord(s.done, stream) != hipSuccess) return IRF_ERR_HIP;
         if (hipGetLastError() != hipSuccess) return IRF_ERR_HIP;

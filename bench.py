@@ -31,6 +31,9 @@ if ROOT not in sys.path:
 
 METRIC = "filtered megapixels/sec at bit-exact output; batched vs per-frame; p99 frame latency"
 HBM_PEAK_GBS = 8000.0
+# vector ALU issue rate: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz, in
+# lane-instructions per second (a packed 16-bit instruction counts once)
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 W, H = 640, 512
 BYTES_PER_PX = 4  # uint16 read once + written once per pass
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_u16.json")
@@ -58,8 +61,8 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(window: int):
-    """HBM bytes per launch measured by rocprofv3 counters, if taken on this source."""
+def _counter_record(window: int):
+    """The counter record of one window's kernel, if it was taken on this source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -67,8 +70,29 @@ def load_traffic(window: int):
         return None
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    ent = rec.get("windows", {}).get(str(window))
+    return rec.get("windows", {}).get(str(window))
+
+
+def load_traffic(window: int):
+    """HBM bytes per launch measured by rocprofv3 counters, if taken on this source."""
+    ent = _counter_record(window)
     return None if ent is None else float(ent["hbm_bytes_per_launch"])
+
+
+def load_valu(window: int):
+    """VALU instructions (wave-level) per launch from SQ_INSTS_VALU, if taken on this source."""
+    ent = _counter_record(window)
+    return None if ent is None or "valu_insts_per_launch" not in ent else float(ent["valu_insts_per_launch"])
+
+
+def _fnr_u16_window(name: str):
+    """The window of a 16-bit single-size FNR kernel's name, else None."""
+    if "fnr_persistent_kernel<unsigned short," not in name:
+        return None
+    targs = [x.strip() for x in name.split("fnr_persistent_kernel<", 1)[1].split(">", 1)[0].split(",")]
+    if len(targs) < 3 or targs[2] != "1":  # MODE_FNR only
+        return None
+    return int(targs[1])
 
 
 def ingest_counters(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out_path=TRAFFIC_FILE) -> dict:
@@ -102,16 +126,36 @@ def ingest_counters(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out_path=TRAFF
         "bytes": 1 << 30, "fetch_kib": fk, "write_kib": wk, "fetch_scale": ff, "write_scale": wf},
         "windows": {}}
     for name, vs in fetch.items():
-        if "fnr_persistent_kernel<unsigned short," not in name:
+        k = _fnr_u16_window(name)
+        if k is None:
             continue
-        targs = [x.strip() for x in name.split("fnr_persistent_kernel<", 1)[1].split(">", 1)[0].split(",")]
-        if len(targs) < 3 or targs[2] != "1":  # MODE_FNR only
-            continue
-        k = int(targs[1])
         f_kib = sum(vs) / len(vs)
         w_kib = sum(write[name]) / len(write[name])
         rec["windows"][str(k)] = {"kernel": name, "fetch_kib": f_kib, "write_kib": w_kib,
                                   "hbm_bytes_per_launch": f_kib * 1024 * ff + w_kib * 1024 * wf}
+    with open(out_path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+def ingest_sq(sq_csv, out_path=TRAFFIC_FILE) -> dict:
+    """Adds SQ_INSTS_VALU per launch (a rocprofv3 --pmc run over the same
+    command, on the same sources) to the counter record."""
+    import csv
+
+    with open(out_path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        raise SystemExit("the counter record was taken on other sources; take FETCH_SIZE/WRITE_SIZE again first")
+    vals = {}
+    with open(sq_csv) as fh:
+        for r in csv.DictReader(fh):
+            k = _fnr_u16_window(r["Kernel_Name"])
+            if k is not None and r["Counter_Name"] == "SQ_INSTS_VALU":
+                vals.setdefault(k, []).append(float(r["Counter_Value"]))
+    for k, vs in vals.items():
+        if str(k) in rec["windows"]:
+            rec["windows"][str(k)]["valu_insts_per_launch"] = sum(vs) / len(vs)
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
@@ -542,10 +586,15 @@ def main() -> int:
                     help="skip the autotuner and run the library's untuned choices")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write the HBM traffic record from rocprofv3 counter CSVs and exit")
+    ap.add_argument("--ingest-sq", metavar="SQ_CSV",
+                    help="add SQ_INSTS_VALU per launch from a rocprofv3 counter CSV to that record and exit")
     args = ap.parse_args()
 
-    if args.ingest_counters:
-        print(json.dumps(ingest_counters(*args.ingest_counters)), flush=True)
+    if args.ingest_counters or args.ingest_sq:
+        if args.ingest_counters:
+            print(json.dumps(ingest_counters(*args.ingest_counters)), flush=True)
+        if args.ingest_sq:
+            print(json.dumps(ingest_sq(args.ingest_sq)), flush=True)
         return 0
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -665,11 +714,20 @@ def main() -> int:
     bytes_per_launch = BYTES_PER_PX * N * W * H
     achieved = bytes_per_launch / (kern_ms[dom] * 1e-3) / 1e9
     traffic = load_traffic(dom)
+    # the vector ALU view of the same launch: the kernel is bound by its
+    # integer work before the HBM roofline (wave instructions x 64 lanes)
+    valu_insts = load_valu(dom)
+    valu = None
+    if valu_insts is not None:
+        lane_t = valu_insts * 64 / (kern_ms[dom] * 1e-3) / 1e12
+        valu = {"insts_per_launch": valu_insts, "slots_per_px": round(valu_insts * 64 / (N * W * H), 2),
+                "achieved": round(lane_t, 2), "peak": round(VALU_PEAK_T, 2), "unit": "T lane-instructions/s",
+                "frac": round(lane_t / VALU_PEAK_T, 4)}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": f"fnr_persistent_kernel<u16,{dom},FNR,{chosen[dom][0]},"
                           f"{irfilter.SELECT_NAMES[chosen[dom][1]]}>",
-                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "algorithmic_bytes_per_launch": bytes_per_launch, "valu": valu,
                 "per_window_GBps": {str(k): round(bytes_per_launch / (kern_ms[k] * 1e-3) / 1e9, 1)
                                     for k in windows}}
 

@@ -206,7 +206,12 @@ __device__ __forceinline__ uint4 load_chunk(const uint8_t *frame, uint32_t row_o
 // t + NT, ... (chunk h is number h % (2 HC) of row h / (2 HC), the left ones
 // first), so a thread's column is the same on every tile.  All loads are
 // issued before the first LDS write.
-template <typename T, int K, int NT = kThreads, bool HALF = false>
+//
+// EARLY (the persistent stack kernel): the workgroup barrier that frees the
+// previous tile's LDS is taken here, after this thread's global loads are
+// issued and before its LDS writes, so the wait at the barrier overlaps the
+// loads' latency; the loads are issued at the highest wave priority.
+template <typename T, int K, int NT = kThreads, bool HALF = false, bool EARLY = false>
 __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
                                           int y0, bool aligned, uint16_t *tile) {
     using G = Geometry<K, NT>;
@@ -220,6 +225,7 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
     const int cx = tid & 15, row0 = tid >> 4;
     const int ytop = y0 - G::r;
     uint4 v[kRounds], h[kHRounds];
+    if constexpr (EARLY) __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int j = 0; j < kRounds; ++j) {
         const int row = row0 + j * kStep;
@@ -238,6 +244,10 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
             h[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 - G::halo + 8 * hcol,
                                        W, aligned);
         }
+    }
+    if constexpr (EARLY) {
+        __builtin_amdgcn_s_setprio(0);
+        __syncthreads();
     }
 #pragma unroll
     for (int j = 0; j < kRounds; ++j) {
@@ -1016,8 +1026,9 @@ __device__ __forceinline__ void dense3_block(const uint16_t *tile, int strip, in
 // the calling thread's pixels only: reading another thread's pixels needs a
 // barrier first.  `rot` rotates which wave starts the list; pk_one is the
 // host's 0x00010001 (see median_registers).  Returns the number of flagged
-// pixels of the calling wave (wave-uniform).
-template <int K, int NT, int SEL>
+// pixels of the calling wave (wave-uniform).  PRIO: the wave runs from here on
+// at the highest priority and the caller lowers it again (see process_tile).
+template <int K, int NT, int SEL, bool PRIO = false>
 __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32_t flags, int centre0,
                                                      int rot, uint32_t pk_one) {
     using G = Geometry<K, NT>;
@@ -1025,6 +1036,7 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
                   "no kernel of this selection for this window");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
     const uint32_t cnt = __builtin_popcount(flags);
     const uint32_t incl = wave_inclusive_sum(cnt);
     const uint32_t wave_total = __builtin_amdgcn_readlane(incl, 63);
@@ -1090,7 +1102,15 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
 // One tile already staged in LDS: detection, compaction of the flagged pixels,
 // selection, then the tile (flagged pixels replaced) is stored.  Returns the
 // number of flagged pixels the calling wave found (wave-uniform).
-template <typename T, int K, int MODE, int NT = kThreads, int SEL = default_select(K)>
+//
+// PRIO (the persistent stack kernel): detection, the long phase that every
+// wave of the workgroup runs alike, keeps the lowest wave priority; compaction,
+// selection, write-back and store run at the highest.  A workgroup's waves that
+// the others wait for at a barrier (those holding selection work) then issue
+// ahead of other workgroups' detection, which fills the gaps; with the loads
+// also issued at the highest priority (load_tile, EARLY), this measured 9-12%
+// faster at 5x5 to 9x9.
+template <typename T, int K, int MODE, int NT = kThreads, int SEL = default_select(K), bool PRIO = false>
 __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K, NT> &sm) {
     using G = Geometry<K, NT>;
     static_assert(SEL == kSelectGroup || (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
@@ -1177,7 +1197,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         return wave_total;
     } else {
         const int centre0 = (strip * R + G::r) * G::pitch + G::halo + 4 * tx;
-        const uint32_t wave_total = median_into_tile<K, NT, SEL>(sm, flags, centre0, tile, a.pk_one);
+        const uint32_t wave_total = median_into_tile<K, NT, SEL, PRIO>(sm, flags, centre0, tile, a.pk_one);
         // 5. store the thread's block (its own LDS values only: no barrier needed)
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
         const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform
@@ -1198,6 +1218,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
                 store4<T>(dst, ro, px, W, aligned, c[0], c[1]);
             }
         }
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         return wave_total;
     }
 }
@@ -1212,9 +1233,11 @@ __device__ __forceinline__ void tile_origin(const StackArgs &a, int tile, int th
 }
 
 // Persistent kernel: every workgroup loops over its tile range.  Four
-// barriers per tile: before the LDS tile is overwritten, after it is written,
-// after the flagged list is complete and after the selection.  Other resident
-// workgroups run while one waits for its tile's loads.
+// barriers per tile: before the LDS tile is overwritten (taken once the tile's
+// global loads are issued), after it is written, after the flagged list is
+// complete and after the selection.  Other resident workgroups run while one
+// waits for its tile's loads; wave priorities favour every phase but
+// detection (process_tile).
 template <typename T, int K, int MODE, int NT, int SEL>
 __global__ __launch_bounds__(NT) void fnr_persistent_kernel(StackArgs a) {
     using G = Geometry<K, NT>;
@@ -1225,12 +1248,12 @@ __global__ __launch_bounds__(NT) void fnr_persistent_kernel(StackArgs a) {
     for (int t = rg.first; t < rg.end; t += rg.stride) {
         int f, x0, y0;
         tile_origin(a, t, G::TH, f, x0, y0);
-        __syncthreads();  // the previous tile is no longer read
-        load_tile<T, K, NT>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, a.width, a.height, x0, y0,
-                        aligned, sm.tile);
+        // includes the barrier after which the previous tile is no longer read
+        load_tile<T, K, NT, false, true>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, a.width, a.height,
+                                         x0, y0, aligned, sm.tile);
         if (threadIdx.x == 0) sm.count = 0;
         __syncthreads();
-        flagged += process_tile<T, K, MODE, NT, SEL>(a, t, sm);
+        flagged += process_tile<T, K, MODE, NT, SEL, true>(a, t, sm);
     }
     if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR || MODE == MODE_DETECT_DIR) {
         if (a.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)

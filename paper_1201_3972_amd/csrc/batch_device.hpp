@@ -50,6 +50,9 @@ __host__ __device__ constexpr int batch_class(int window) {
     return window <= kBatchClassMax[0] ? 0 : (window <= kBatchClassMax[1] ? 1 : 2);
 }
 
+// One tile of the queue, with the stack kernel's issue order: the tile's global
+// loads go out before the barrier that frees the LDS of the previous tile
+// (inside load_tile), and wave priorities favour every phase but detection.
 template <typename T, int K, int NT>
 __device__ __forceinline__ uint32_t batch_tile(const FrameDesc &d, int local, unsigned char *smem,
                                                uint32_t ticket, unsigned int *s_next, uint32_t pk_one) {
@@ -69,13 +72,13 @@ __device__ __forceinline__ uint32_t batch_tile(const FrameDesc &d, int local, un
     a.pk_one = pk_one;
     int f, x0, y0;
     tile_origin(a, local, G::TH, f, x0, y0);
-    load_tile<T, K, NT>(a.src, a.src_pitch, a.width, a.height, x0, y0, a.aligned != 0, sm.tile);
+    load_tile<T, K, NT, false, true>(a.src, a.src_pitch, a.width, a.height, x0, y0, a.aligned != 0, sm.tile);
     if (threadIdx.x == 0) {
         sm.count = 0;
         *s_next = ticket;  // the loads were waited for, so the atomic has returned too
     }
     __syncthreads();
-    return process_tile<T, K, MODE_FNR, NT>(a, local, sm);
+    return process_tile<T, K, MODE_FNR, NT, default_select(K), true>(a, local, sm);
 }
 
 template <int CLASS, int NT>
@@ -84,8 +87,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kBatchClassW
                                                              BatchQueue *queue, uint32_t pk_one) {
     constexpr int KMAX = kBatchClassMax[CLASS];
     __shared__ __attribute__((aligned(16))) unsigned char smem[sizeof(TileSmem<KMAX, NT>)];
-    // next-tile slots alternate by iteration: thread 0 fills slot (i+1)&1 while
-    // slow threads may still be reading slot i&1 after the last barrier
+    // next-tile slots alternate by iteration: thread 0 fills slot i&1 of
+    // iteration i before the barrier that follows the tile's load, and every
+    // thread reads it at the end of the iteration; the next write to that slot
+    // (iteration i+2) lies behind the barriers of iteration i+1
     __shared__ unsigned int s_next[2];
     const unsigned int total = queue->total;
     if (threadIdx.x == 0) s_next[0] = atomicAdd(&queue->next, 1u);
@@ -125,8 +130,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kBatchClassW
         }
         if (d.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)
             atomicAdd(d.count, (unsigned long long)flagged);
-        __syncthreads();  // the tile's LDS is free; the slot holds the next ticket
-        t = *slot;
+        t = *slot;  // the barrier inside the next load_tile frees this tile's LDS
     }
 }
 

@@ -35,7 +35,10 @@ struct FusedGeometry {
 // (ox, oy) = (kFusedTileW * (t % tiles_x), out_rows * (t / tiles_x)) and its
 // block at (ox - 4, oy - r).  Counts: a.count[0] += pass-1 flags and
 // a.count[1] += pass-2 flags, each over the output pixels only, so that every
-// pixel of the frame is counted once per pass.
+// pixel of the frame is counted once per pass.  Issue order as in the stack
+// kernel: the block's loads go out before the barrier that frees the previous
+// block's LDS, and both detections run at the lowest wave priority, every
+// other phase at the highest.
 template <typename T, int K, int NT, int SEL>
 __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
     using G = Geometry<K, NT>;
@@ -55,8 +58,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
         const int ty = rem / a.tiles_x;
         const int ox = (rem - ty * a.tiles_x) * kFusedTileW, oy = ty * OH;
         const int x0 = ox - 4, y0 = oy - r;
-        __syncthreads();  // the previous tile is no longer read
-        load_tile<T, K, NT, true>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, W, H, x0, y0, aligned,
+        load_tile<T, K, NT, true, true>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, W, H, x0, y0, aligned,
                                   sm.tile);
         if (tid == 0) sm.count = 0;
         __syncthreads();
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
             for (int q = 0; q < R; ++q)
                 *reinterpret_cast<uint2 *>(sm.tile + centre0 + q * G::pitch) = make_uint2(o1[q][0], o1[q][1]);
         } else {
-            median_into_tile<K, NT, SEL>(sm, f1, centre0, t, a.pk_one);
+            median_into_tile<K, NT, SEL, true>(sm, f1, centre0, t, a.pk_one);
         }
         if (tid == 0) sm.count = 0;  // every thread read the pass-1 list length before its selection
         __syncthreads();
@@ -97,13 +99,14 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
         }
 
         // pass 2 on the output pixels
+        __builtin_amdgcn_s_setprio(0);
         const uint32_t f2 = detect_block<K>(sm.tile, strip, tx, a.pk_one) & out;
         n2 += __builtin_popcount(f2);
         uint32_t o2[R][2];
         if constexpr (K == 3) {
             dense3_block<R>(sm.tile, strip, tx, f2, o2);
         } else {
-            median_into_tile<K, NT, SEL>(sm, f2, centre0, t, a.pk_one);
+            median_into_tile<K, NT, SEL, true>(sm, f2, centre0, t, a.pk_one);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const uint2 c = *reinterpret_cast<const uint2 *>(sm.tile + centre0 + q * G::pitch);
@@ -114,6 +117,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
 
         // store the thread's output pixels (a thread holds whole 4-column groups
         // of the output, or none; the last tile of a row may end inside one)
+        __builtin_amdgcn_s_setprio(3);
         if (out != 0) {
             uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
             const int xend = min(ox + kFusedTileW, W);
@@ -124,6 +128,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
                 store4<T>(dst, ro, px, xend, aligned, o2[q][0], o2[q][1]);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
     }
     if (a.count != nullptr) {
         const uint32_t s1 = __builtin_amdgcn_readlane(wave_inclusive_sum(n1), 63);

@@ -1105,7 +1105,8 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
 //
 // PRIO (the persistent stack kernel): detection, the long phase that every
 // wave of the workgroup runs alike, keeps the lowest wave priority; compaction,
-// selection, write-back and store run at the highest.  A workgroup's waves that
+// selection, write-back and store (at 3x3 the store after the dense medians)
+// run at the highest.  A workgroup's waves that
 // the others wait for at a barrier (those holding selection work) then issue
 // ahead of other workgroups' detection, which fills the gaps; with the loads
 // also issued at the highest priority (load_tile, EARLY), this measured 9-12%
@@ -1175,6 +1176,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         const uint32_t wave_total = __builtin_amdgcn_readlane(wave_inclusive_sum(__builtin_popcount(flags)), 63);
         uint32_t out[R][2];
         dense3_block<R>(sm.tile, strip, tx, flags, out);
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
         const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform
 #pragma unroll
@@ -1194,6 +1196,7 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
                 store4<T>(dst, ro, px, W, aligned, out[q][0], out[q][1]);
             }
         }
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         return wave_total;
     } else {
         const int centre0 = (strip * R + G::r) * G::pitch + G::halo + 4 * tx;

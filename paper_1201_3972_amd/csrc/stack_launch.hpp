@@ -51,7 +51,8 @@ inline int fused_tile_rows(int window, int threads) {
 constexpr int kFusionAuto = -1;
 // The automatic choice for a W x H frame whose single passes run with
 // plain_threads: the fused workgroup size whose tiles cover the fewest pixels,
-// if they cover no more than the plain tiles of two separate passes, else 0.
+// if they cover no more than the plain tiles of two separate passes (at 3x3:
+// fewer), else 0.
 // Both kernels are bound by vector ALU work per covered pixel, so fusion only
 // pays where its overlapping tiles cost no extra work (6 fused tiles of 120
 // output columns cover a 640-pixel row that 5 plain tiles cover, for one).
@@ -60,12 +61,15 @@ inline int auto_fusion(int width, int height, int window, int plain_threads) {
     auto cdiv = [](long long a, long long b) { return (a + b - 1) / b; };
     const long long ph = plain_threads / kThreadsX * Geometry<3>::R;
     const long long plain = 2 * cdiv(width, kTileW) * cdiv(height, ph) * kTileW * ph;
+    // at 3x3 both forms compute every median in registers and separate passes
+    // win at equal coverage; larger windows fuse at equal coverage
+    const bool strict = window == 3;
     int best = 0;
     long long best_px = plain;
     for (int t : {256, 512}) {
         const long long th = t / kThreadsX * Geometry<3>::R;
         const long long px = 2 * cdiv(width, kFusedTileW) * cdiv(height, fused_tile_rows(window, t)) * kTileW * th;
-        if (px <= best_px && (best == 0 || px < best_px)) {
+        if (px < best_px || (px == best_px && best == 0 && !strict)) {
             best = t;
             best_px = px;
         }

@@ -109,7 +109,7 @@ def test_automatic_fusion_covers_no_more_pixels(dt, k, W, H):
     base = _covered(W, H, k, 0, plain)
     options = {t: _covered(W, H, k, t, plain) for t in (256, 512)}
     best = min(options.values())
-    if best > base:
+    if best > base or (k == 3 and best == base):  # 3x3 fuses only on strictly fewer pixels
         assert got == 0
     else:
         assert got in options and options[got] == best
@@ -117,12 +117,15 @@ def test_automatic_fusion_covers_no_more_pixels(dt, k, W, H):
 
 
 def test_resolve_fusion_follows_the_setting():
-    assert irfilter.resolve_fusion("u8", 3, 320, 240) == 256  # equal coverage: fused
+    assert irfilter.resolve_fusion("u8", 5, 320, 240) == 256  # equal coverage: fused
+    assert irfilter.resolve_fusion("u8", 3, 320, 240) == 0    # ... except at 3x3
     assert irfilter.resolve_fusion("u16", 5, 640, 512) == 0   # 6 fused tiles across vs 5 plain
     irfilter.set_fusion("u16", 5, 512)
     assert irfilter.resolve_fusion("u16", 5, 640, 512) == 512
-    irfilter.set_fusion("u8", 3, 0)
-    assert irfilter.resolve_fusion("u8", 3, 320, 240) == 0
+    irfilter.set_fusion("u8", 3, 256)
+    assert irfilter.resolve_fusion("u8", 3, 320, 240) == 256
+    irfilter.set_fusion("u8", 5, 0)
+    assert irfilter.resolve_fusion("u8", 5, 320, 240) == 0
     lib = irfilter.load()
     assert lib.ir_filter_resolve_fusion(2, 5, 0, 10, None) == -1
     import ctypes

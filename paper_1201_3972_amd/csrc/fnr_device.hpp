@@ -207,10 +207,11 @@ __device__ __forceinline__ uint4 load_chunk(const uint8_t *frame, uint32_t row_o
 // first), so a thread's column is the same on every tile.  All loads are
 // issued before the first LDS write.
 //
-// EARLY (the persistent stack kernel): the workgroup barrier that frees the
-// previous tile's LDS is taken here, after this thread's global loads are
-// issued and before its LDS writes, so the wait at the barrier overlaps the
-// loads' latency; the loads are issued at the highest wave priority.
+// EARLY (the persistent stack, batch and fused kernels): the workgroup
+// barrier that frees the previous tile's LDS is taken here, after this
+// thread's global loads are issued and before its LDS writes, so the wait at
+// the barrier overlaps the loads' latency; the loads are issued at the highest
+// wave priority.
 template <typename T, int K, int NT = kThreads, bool HALF = false, bool EARLY = false>
 __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
                                           int y0, bool aligned, uint16_t *tile) {
@@ -1103,14 +1104,14 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
 // selection, then the tile (flagged pixels replaced) is stored.  Returns the
 // number of flagged pixels the calling wave found (wave-uniform).
 //
-// PRIO (the persistent stack kernel): detection, the long phase that every
-// wave of the workgroup runs alike, keeps the lowest wave priority; compaction,
-// selection, write-back and store (at 3x3 the store after the dense medians)
-// run at the highest.  A workgroup's waves that
-// the others wait for at a barrier (those holding selection work) then issue
-// ahead of other workgroups' detection, which fills the gaps; with the loads
-// also issued at the highest priority (load_tile, EARLY), this measured 9-12%
-// faster at 5x5 to 9x9.
+// PRIO (the persistent stack and batch kernels): detection, the long phase
+// that every wave of the workgroup runs alike, keeps the lowest wave priority;
+// compaction, selection, write-back and store (at 3x3 the store after the
+// dense medians) run at the highest.  A workgroup's waves that the others wait
+// for at a barrier (those holding selection work) then issue ahead of other
+// workgroups' detection, which fills the gaps; with the loads also issued at
+// the highest priority (load_tile, EARLY), this measured 9-12% faster at 5x5
+// to 9x9.
 template <typename T, int K, int MODE, int NT = kThreads, int SEL = default_select(K), bool PRIO = false>
 __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K, NT> &sm) {
     using G = Geometry<K, NT>;

@@ -192,10 +192,45 @@ __device__ __forceinline__ uint4 load_chunk(const uint8_t *frame, uint32_t row_o
     }
     if (gx + 8 <= 0) return splat8(load_px<T>(frame, row_off, 0));
     if (gx >= W) return splat8(load_px<T>(frame, row_off, W - 1));
+    // chunks that cross an edge are rare: an empty asm makes gx opaque here,
+    // so the compiler does not compute the eight clamped columns for every
+    // tile ahead of the branch
+    asm volatile("" : "+v"(gx));
     uint32_t e[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) e[i] = load_px<T>(frame, row_off, min(max(gx + i, 0), W - 1));
     return make_uint4(e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16));
+}
+
+// A raw buffer resource over a frame (no range limit beyond 4 GiB; the host
+// keeps every frame's span below that): loads through it take a per-thread
+// 32-bit offset and a wave-uniform 32-bit offset in a scalar register, so a
+// row offset that is the same for the whole wave costs no vector instruction.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const uint8_t *frame) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(frame), (short)0, -1, 0x00020000);
+}
+
+// One 8-pixel chunk that lies wholly inside the frame on a 16-byte-aligned
+// layout, at byte offset voff + soff (soff wave-uniform) from the frame base.
+template <typename T, bool HALF>
+__device__ __forceinline__ uint4 load_inside(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+    if constexpr (HALF) {
+        if constexpr (sizeof(T) == 2) {
+            const auto lo = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0);
+            const auto hi = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(voff + 8u), (int)soff, 0);
+            return make_uint4(lo[0], lo[1], hi[0], hi[1]);
+        } else {
+            const uint32_t lo = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, (int)soff, 0);
+            const uint32_t hi = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(voff + 4u), (int)soff, 0);
+            return widen8(make_uint2(lo, hi));
+        }
+    } else if constexpr (sizeof(T) == 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, (int)soff, 0);
+        return make_uint4(v[0], v[1], v[2], v[3]);
+    } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, (int)soff, 0);
+        return widen8(make_uint2(v[0], v[1]));
+    }
 }
 
 // Stage rows y0-r .. y0+TH+r-1 and columns x0-halo .. x0+kTileW+halo-1 of a
@@ -206,6 +241,13 @@ __device__ __forceinline__ uint4 load_chunk(const uint8_t *frame, uint32_t row_o
 // t + NT, ... (chunk h is number h % (2 HC) of row h / (2 HC), the left ones
 // first), so a thread's column is the same on every tile.  All loads are
 // issued before the first LDS write.
+//
+// Addressing: within a round, a thread's chunk sits at a fixed offset from
+// the wave's first row and the tile's first column, which are wave-uniform.
+// When the rows a wave loads in a round lie inside the frame and the tile's
+// columns (interior, or halo) do too (every round of most tiles), the load is
+// a buffer load at that fixed offset plus a scalar one; only the other rounds
+// clamp rows and columns per thread.
 //
 // EARLY (the persistent stack, batch and fused kernels): the workgroup
 // barrier that frees the previous tile's LDS is taken here, after this
@@ -221,29 +263,53 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
     constexpr int HC = G::halo / 8;                    // halo chunks on each side
     constexpr int kHalos = 2 * HC * G::rows;           // halo chunks of the tile
     constexpr int kHRounds = (kHalos + NT - 1) / NT;
+    constexpr int kHStep = NT / (2 * HC);              // halo rows per round
+    constexpr int kHWave = 64 / (2 * HC);              // halo rows of a wave in a round
+    constexpr uint32_t b = sizeof(T);
     static_assert(kTileW == 16 * 8 && G::chunks == 16 + 2 * HC, "16 interior chunks per row");
     const int tid = threadIdx.x;
     const int cx = tid & 15, row0 = tid >> 4;
     const int ytop = y0 - G::r;
+    const uint32_t p32 = (uint32_t)pitch;
+    const __amdgpu_buffer_rsrc_t rs = frame_rsrc(src);
+    // wave-uniform: the wave's first interior and halo row within a round, and
+    // whether the tile's interior and halo columns lie inside the frame
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wrow = wave * 4, whrow = wave * kHWave;
+    const bool in_x = aligned && x0 >= 0 && x0 + kTileW <= W;
+    const bool in_xh = aligned && x0 - G::halo >= 0 && x0 + kTileW + G::halo <= W;
+    // per thread: column and offset from the wave's first row
+    const int gx = x0 + 8 * cx;
+    const uint32_t voff = (uint32_t)(row0 & 3) * p32 + 8u * b * (uint32_t)cx;
+    const int which = tid % (2 * HC), hrow0 = tid / (2 * HC);
+    const int hcol = HC == 1 ? (which ? G::chunks - 1 : 0) : (which < HC ? which : 16 + which);
+    const int gxh = x0 - G::halo + 8 * hcol;
+    const uint32_t voffh = (uint32_t)(hrow0 - whrow) * p32 + 8u * b * (uint32_t)hcol;
     uint4 v[kRounds], h[kHRounds];
     if constexpr (EARLY) __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int j = 0; j < kRounds; ++j) {
         const int row = row0 + j * kStep;
-        if (j < kRounds - 1 || row < G::rows) {
+        const int first = ytop + j * kStep + wrow;  // the wave's rows: first .. first + 3
+        if (in_x && first >= 0 && first + 3 < H) {
+            if (j < kRounds - 1 || row < G::rows)
+                v[j] = load_inside<T, HALF>(rs, voff, (uint32_t)first * p32 + (uint32_t)x0 * b);
+        } else if (j < kRounds - 1 || row < G::rows) {
             const int gy = min(max(ytop + row, 0), H - 1);
-            v[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 + 8 * cx, W, aligned);
+            v[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, p32), gx, W, aligned);
         }
     }
 #pragma unroll
     for (int j = 0; j < kHRounds; ++j) {
         const int hc = tid + j * NT;
-        if (hc < kHalos) {
-            const int hrow = hc / (2 * HC), which = hc % (2 * HC);
-            const int hcol = HC == 1 ? ((hc & 1) ? G::chunks - 1 : 0) : (which < HC ? which : 16 + which);
+        const int hrow = hrow0 + j * kHStep;
+        const int first = ytop + j * kHStep + whrow;  // the wave's halo rows: first .. first + kHWave - 1
+        if (in_xh && first >= 0 && first + kHWave - 1 < H) {
+            if (hc < kHalos)
+                h[j] = load_inside<T, HALF>(rs, voffh, (uint32_t)first * p32 + (uint32_t)(x0 - G::halo) * b);
+        } else if (hc < kHalos) {
             const int gy = min(max(ytop + hrow, 0), H - 1);
-            h[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, (uint32_t)pitch), x0 - G::halo + 8 * hcol,
-                                       W, aligned);
+            h[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, p32), gxh, W, aligned);
         }
     }
     if constexpr (EARLY) {
@@ -260,8 +326,7 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
     for (int j = 0; j < kHRounds; ++j) {
         const int hc = tid + j * NT;
         if (hc < kHalos) {
-            const int hrow = hc / (2 * HC), which = hc % (2 * HC);
-            const int hcol = HC == 1 ? ((hc & 1) ? G::chunks - 1 : 0) : (which < HC ? which : 16 + which);
+            const int hrow = hrow0 + j * kHStep;
             *reinterpret_cast<uint4 *>(tile + hrow * G::pitch + 8 * hcol) = h[j];
         }
     }
@@ -928,6 +993,42 @@ __device__ __forceinline__ void store4(uint8_t *frame, uint32_t row_off, int px,
     }
 }
 
+// The thread's 4 x R output block (columns px..px+3, rows py..py+R-1 of a
+// tile at x0, y0) to the frame; pair(q, p0, p1) gives row q's two packed pairs.
+// A tile wholly inside the frame on an aligned layout (`full`, uniform) stores
+// each row at a wave-uniform base (the tile's row q) plus the thread's fixed
+// offset, so the address costs no vector instruction; other tiles clip per
+// row and per pixel.
+template <typename T, int R, typename Pair>
+__device__ __forceinline__ void store_block(uint8_t *frame, uint64_t pitch, int x0, int y0, int px, int py,
+                                            int W, int H, bool aligned, bool full, Pair &&pair) {
+    const uint32_t p32 = (uint32_t)pitch;
+    if (full) {
+        const uint32_t off = (uint32_t)(py - y0) * p32 + (uint32_t)(px - x0) * (uint32_t)sizeof(T);
+        uint8_t *base = frame + (int64_t)y0 * (int64_t)pitch + (int64_t)x0 * (int64_t)sizeof(T);
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            uint32_t p0, p1;
+            pair(q, p0, p1);
+            uint8_t *row = base + (int64_t)q * (int64_t)pitch;
+            if constexpr (sizeof(T) == 2) {
+                *reinterpret_cast<uint2 *>(row + off) = make_uint2(p0, p1);
+            } else {
+                *reinterpret_cast<uint32_t *>(row + off) =
+                    (p0 & 0xffu) | ((p0 >> 8) & 0xff00u) | ((p1 & 0xffu) << 16) | ((p1 & 0xff0000u) << 8);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (py + q >= H) break;
+            uint32_t p0, p1;
+            pair(q, p0, p1);
+            store4<T>(frame, __umul24((uint32_t)(py + q), p32), px, W, aligned, p0, p1);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the tile kernel
 // ---------------------------------------------------------------------------
@@ -1180,23 +1281,11 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
         const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            if (!full && py + q >= H) break;
-            const uint32_t ro = __umul24((uint32_t)(py + q), (uint32_t)a.dst_pitch);
-            if (full) {
-                const uint32_t off = ro + (uint32_t)px * (uint32_t)sizeof(T);
-                if constexpr (sizeof(T) == 2) {
-                    *reinterpret_cast<uint2 *>(dst + off) = make_uint2(out[q][0], out[q][1]);
-                } else {
-                    *reinterpret_cast<uint32_t *>(dst + off) =
-                        (out[q][0] & 0xffu) | ((out[q][0] >> 8) & 0xff00u) | ((out[q][1] & 0xffu) << 16) |
-                        ((out[q][1] & 0xff0000u) << 8);
-                }
-            } else {
-                store4<T>(dst, ro, px, W, aligned, out[q][0], out[q][1]);
-            }
-        }
+        store_block<T, R>(dst, a.dst_pitch, x0, y0, px, py, W, H, aligned, full,
+                          [&](int q, uint32_t &p0, uint32_t &p1) {
+                              p0 = out[q][0];
+                              p1 = out[q][1];
+                          });
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         return wave_total;
     } else {
@@ -1205,23 +1294,12 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, T
         // 5. store the thread's block (its own LDS values only: no barrier needed)
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
         const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            if (!full && py + q >= H) break;
-            const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * G::pitch);
-            const uint32_t ro = __umul24((uint32_t)(py + q), (uint32_t)a.dst_pitch);
-            if (full) {
-                const uint32_t off = ro + (uint32_t)px * (uint32_t)sizeof(T);
-                if constexpr (sizeof(T) == 2) {
-                    *reinterpret_cast<uint2 *>(dst + off) = make_uint2(c[0], c[1]);
-                } else {
-                    *reinterpret_cast<uint32_t *>(dst + off) = (c[0] & 0xffu) | ((c[0] >> 8) & 0xff00u) |
-                                                               ((c[1] & 0xffu) << 16) | ((c[1] & 0xff0000u) << 8);
-                }
-            } else {
-                store4<T>(dst, ro, px, W, aligned, c[0], c[1]);
-            }
-        }
+        store_block<T, R>(dst, a.dst_pitch, x0, y0, px, py, W, H, aligned, full,
+                          [&](int q, uint32_t &p0, uint32_t &p1) {
+                              const uint32_t *c = reinterpret_cast<const uint32_t *>(sm.tile + centre0 + q * G::pitch);
+                              p0 = c[0];
+                              p1 = c[1];
+                          });
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
         return wave_total;
     }

@@ -122,13 +122,16 @@ irf_status ir_filter_median(const void *src, size_t src_pitch, const uint8_t *ma
 
 /*
  * ir_filter_run -- the whole FNR filter, `passes` times (Sections 3.3-3.4, 4).
- *   Detection and median replacement are fused in one kernel per pass.
+ *   Detection and median replacement are fused in one kernel per pass; pairs of
+ *   passes may run as one fused launch instead (ir_filter_set_fusion,
+ *   ir_filter_resolve_fusion), with the same results and per-pass counts.
  *   passes               1..IRF_MAX_PASSES; pass i reads the output of pass i-1
  *   scratch, scratch_pitch  device frame of the same size and type, required when
  *                        passes >= 2 (intermediate passes alternate between it and
  *                        dst so that the last one lands in dst); ignored otherwise
  *   flagged_count        nullable device array of `passes` uint64: noisy pixels found
- *                        by each pass (zeroed on the stream, then accumulated)
+ *                        by each pass (zeroed on the stream, then accumulated); it
+ *                        must not overlap src, dst or scratch (IRF_ERR_ALIAS)
  */
 irf_status ir_filter_run(const void *src, size_t src_pitch, void *dst, size_t dst_pitch, int width,
                          int height, irf_dtype dtype, int window, int passes, void *scratch,
@@ -136,7 +139,8 @@ irf_status ir_filter_run(const void *src, size_t src_pitch, void *dst, size_t ds
 
 /*
  * ir_filter_run_frames -- ir_filter_run over a stack of `nframes` frames of the
- * same size, one launch per pass.  Frame i starts at src + i*src_stride (bytes),
+ * same size, one launch per pass (or per fused pair of passes, as for
+ * ir_filter_run).  Frame i starts at src + i*src_stride (bytes),
  * dst + i*dst_stride, scratch + i*scratch_stride.  Frames are filtered
  * independently; flagged_count[p] (nullable, `passes` entries) receives the
  * noisy pixels of pass p summed over all frames.
@@ -274,11 +278,15 @@ irf_status ir_filter_server_run(irf_server *server);
  * server, oldest first; returns how many were written. */
 int ir_filter_server_completed(irf_server *server, uint64_t *ids, double *latency_s, int max);
 
-/* Seconds since the server was created (its clock), its step count, and the
- * arena bytes held by requests in flight. */
+/* Seconds since the server was created (its clock), its step count, the
+ * arena bytes held by requests in flight, and all frame memory the server
+ * holds on the device: the arena plus every registered stream's resident
+ * slots (2 * depth frames each, allocated at registration, outside the
+ * arena). */
 double ir_filter_server_now(const irf_server *server);
 int ir_filter_server_steps(const irf_server *server);
 size_t ir_filter_server_arena_used(const irf_server *server);
+size_t ir_filter_server_resident_bytes(const irf_server *server);
 
 /* Waits for outstanding steps, then releases every device and host resource.
  * NULL is ignored. */

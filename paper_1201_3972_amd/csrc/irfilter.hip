@@ -122,9 +122,14 @@ irf_status run_frames(const void *src, size_t src_pitch, size_t src_stride, void
         if (overlap(xs, ss) || overlap(xs, ds)) return IRF_ERR_ALIAS;
     }
     if (counts) {
+        // the counts are zeroed and accumulated while the passes read src and
+        // write dst and scratch: they may share memory with none of them
         const Span cs = {reinterpret_cast<uintptr_t>(counts),
                          reinterpret_cast<uintptr_t>(counts) + sizeof(uint64_t) * (size_t)passes};
         if (overlap(cs, ss) || overlap(cs, ds)) return IRF_ERR_ALIAS;
+        if (passes >= 2 &&
+            overlap(cs, span_of(scratch, scratch_pitch, scratch_stride, width, height, nframes, b)))
+            return IRF_ERR_ALIAS;
     }
     if ((st = zero_counts(counts, passes, stream))) return st;
     // Pairs of passes run fused where a fused kernel is enabled, an odd last

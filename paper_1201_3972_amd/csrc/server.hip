@@ -15,62 +15,16 @@
 #include <vector>
 
 #include "../../include/irfilter.h"
+#include "arena.hpp"
 #include "host_common.hpp"
 
 namespace {
 
 using irf::host::bytes_of;
+using irf::host::Arena;
+using irf::host::round_up;
 
-constexpr size_t kAlign = 4096;
 constexpr int kMaxInflight = 8;
-
-size_t round_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
-
-// First-fit allocator over offsets of one device buffer; freed blocks coalesce.
-class Arena {
-  public:
-    void reset(size_t capacity) {
-        free_.clear();
-        used_ = 0;
-        if (capacity) free_[0] = capacity;
-    }
-    size_t used() const { return used_; }
-    bool alloc(size_t bytes, size_t *off) {
-        const size_t need = round_up(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= need) {
-                *off = it->first;
-                used_ += need;
-                const size_t rest = it->second - need, start = it->first + need;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        size_t start = off, size = round_up(bytes);
-        used_ -= size;
-        auto next = free_.lower_bound(start);
-        if (next != free_.end() && start + size == next->first) {
-            size += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == start) {
-                prev->second += size;
-                return;
-            }
-        }
-        free_[start] = size;
-    }
-
-  private:
-    std::map<size_t, size_t> free_;  // offset -> size
-    size_t used_ = 0;
-};
 
 struct Slot {
     void *src = nullptr, *dst = nullptr;
@@ -250,8 +204,30 @@ void admit(irf_server *s, std::vector<Item> &out) {
     s->pending.swap(keep);
 }
 
-irf_status issue(irf_server *s, std::vector<Item> &items) {
-    Step st;
+// A step that could not be issued: wait for whatever of it reached the
+// streams, give its events, stream slots and arena blocks back, and return its
+// requests to the front of the pending queue in their order, so the server is
+// left as it was before the step was admitted.
+void abandon_step(irf_server *s, Step &st, std::vector<Item> &items) {
+    (void)hipStreamSynchronize(s->h2d);
+    (void)hipStreamSynchronize(s->compute);
+    (void)hipStreamSynchronize(s->d2h);
+    (void)hipGetLastError();
+    for (hipEvent_t e : {st.in, st.kernel, st.done})
+        if (e) s->events.push_back(e);
+    for (auto it = items.rbegin(); it != items.rend(); ++it) {
+        if (it->slot) {
+            it->slot->busy = false;
+        } else {
+            s->arena.release(it->a_off, it->bytes);
+            s->arena.release(it->b_off, it->bytes);
+        }
+        s->pending.push_front(it->r);
+    }
+    items.clear();
+}
+
+irf_status issue_step(irf_server *s, Step &st, const std::vector<Item> &items) {
     irf_status e;
     if ((e = take_event(s, &st.in)) || (e = take_event(s, &st.kernel)) || (e = take_event(s, &st.done))) return e;
     for (const Item &it : items) {
@@ -278,6 +254,16 @@ irf_status issue(irf_server *s, std::vector<Item> &items) {
             return IRF_ERR_HIP;
     }
     if (hipEventRecord(st.done, s->d2h) != hipSuccess) return IRF_ERR_HIP;
+    return IRF_OK;
+}
+
+irf_status issue(irf_server *s, std::vector<Item> &items) {
+    Step st;
+    const irf_status e = issue_step(s, st, items);
+    if (e) {
+        abandon_step(s, st, items);
+        return e;
+    }
     st.items.swap(items);
     s->inflight.push_back(std::move(st));
     ++s->steps;
@@ -465,6 +451,14 @@ double ir_filter_server_now(const irf_server *s) { return s ? seconds_since(s->t
 int ir_filter_server_steps(const irf_server *s) { return s ? s->steps : 0; }
 
 size_t ir_filter_server_arena_used(const irf_server *s) { return s ? s->arena.used() : 0; }
+
+size_t ir_filter_server_resident_bytes(const irf_server *s) {
+    if (!s) return 0;
+    size_t n = s->arena_bytes;
+    for (const auto &kv : s->streams)
+        for (const Slot &sl : kv.second) n += 2 * sl.pitch * (size_t)sl.height;
+    return n;
+}
 
 void ir_filter_server_destroy(irf_server *s) { free_server(s); }
 

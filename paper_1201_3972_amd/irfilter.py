@@ -62,6 +62,7 @@ SIGNATURES = {
     "ir_filter_server_now": (ctypes.c_double, [_vp]),
     "ir_filter_server_steps": (_i32, [_vp]),
     "ir_filter_server_arena_used": (_sz, [_vp]),
+    "ir_filter_server_resident_bytes": (_sz, [_vp]),
     "ir_filter_server_destroy": (None, [_vp]),
 }
 
@@ -177,14 +178,39 @@ def _same(a, b, what: str):
         raise ValueError(f"{what} must match the source shape and pixel type")
 
 
+def _counts(t, need: int, name: str = "flagged_count"):
+    """Pointer of a device count array of at least ``need`` 64-bit entries
+    (None passes through): the kernels write it with 64-bit atomics, so a host
+    tensor, a narrower type or too few entries is refused here."""
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise ValueError(f"{name} must hold 64-bit integers (torch.int64 or torch.uint64)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < need:
+        raise ValueError(f"{name} needs at least {need} entries, has {t.numel()}")
+    return t.data_ptr()
+
+
+def _mask(mask, src):
+    import torch
+    if mask.dtype != torch.uint8:
+        raise ValueError("mask must be uint8")
+    if tuple(mask.shape) != tuple(src.shape):
+        raise ValueError("mask must have the source shape")
+
+
 def ir_filter_detect(src, mask, window: int, flagged_count=None, stream=None) -> None:
     """Noise mask (uint8, 1 = noisy) of ``src``; optional uint64 count tensor (1 element)."""
     sp, spitch = _frame(src, "src")
     mp, mpitch = _frame(mask, "mask")
     H, W = src.shape
-    if tuple(mask.shape) != (H, W):
-        raise ValueError("mask must have the source shape")
-    cp = None if flagged_count is None else flagged_count.data_ptr()
+    _mask(mask, src)
+    cp = _counts(flagged_count, 1)
     _check("ir_filter_detect", load().ir_filter_detect(sp, spitch, mp, mpitch, W, H, _dtype_code(src),
                                                        window, cp, _stream(stream)))
 
@@ -196,9 +222,8 @@ def ir_filter_detect_directional(src, mask, flagged_count=None, stream=None) -> 
     sp, spitch = _frame(src, "src")
     mp, mpitch = _frame(mask, "mask")
     H, W = src.shape
-    if tuple(mask.shape) != (H, W):
-        raise ValueError("mask must have the source shape")
-    cp = None if flagged_count is None else flagged_count.data_ptr()
+    _mask(mask, src)
+    cp = _counts(flagged_count, 1)
     _check("ir_filter_detect_directional",
            load().ir_filter_detect_directional(sp, spitch, mp, mpitch, W, H, _dtype_code(src), cp,
                                                _stream(stream)))
@@ -207,6 +232,8 @@ def ir_filter_detect_directional(src, mask, flagged_count=None, stream=None) -> 
 def ir_filter_median(src, dst, window: int, mask=None, stream=None) -> None:
     """Window median where ``mask`` != 0 (every pixel when ``mask`` is None)."""
     _same(src, dst, "dst")
+    if mask is not None:
+        _mask(mask, src)
     sp, spitch = _frame(src, "src")
     dp, dpitch = _frame(dst, "dst")
     mp, mpitch = (None, 0) if mask is None else _frame(mask, "mask")
@@ -219,24 +246,30 @@ def ir_filter_run(src, dst, window: int, passes: int = 1, scratch=None, flagged_
                   stream=None) -> None:
     """FNR ``passes`` times; ``flagged_count`` (uint64/int64, ``passes`` elements) is optional."""
     _same(src, dst, "dst")
+    if scratch is not None:
+        _same(src, scratch, "scratch")
     sp, spitch = _frame(src, "src")
     dp, dpitch = _frame(dst, "dst")
     xp, xpitch = (None, 0) if scratch is None else _frame(scratch, "scratch")
     H, W = src.shape
-    cp = None if flagged_count is None else flagged_count.data_ptr()
+    cp = _counts(flagged_count, passes)
     _check("ir_filter_run", load().ir_filter_run(sp, spitch, dp, dpitch, W, H, _dtype_code(src), window,
                                                  passes, xp, xpitch, cp, _stream(stream)))
 
 
 def ir_filter_run_frames(src, dst, window: int, passes: int = 1, scratch=None, flagged_count=None,
                          stream=None) -> None:
-    """FNR over a stack ``[N, H, W]`` in one launch per pass."""
+    """FNR over a stack ``[N, H, W]``: one launch per pass, or per pair of passes
+    where the library fuses two passes into one launch (see ``set_fusion``);
+    results and per-pass counts are the same either way."""
     _same(src, dst, "dst")
+    if scratch is not None:
+        _same(src, scratch, "scratch")
     sp, spitch, sstride = _stack(src, "src")
     dp, dpitch, dstride = _stack(dst, "dst")
     xp, xpitch, xstride = (None, 0, 0) if scratch is None else _stack(scratch, "scratch")
     N, H, W = src.shape
-    cp = None if flagged_count is None else flagged_count.data_ptr()
+    cp = _counts(flagged_count, passes)
     _check("ir_filter_run_frames",
            load().ir_filter_run_frames(sp, spitch, sstride, dp, dpitch, dstride, W, H, N, _dtype_code(src),
                                        window, passes, xp, xpitch, xstride, cp, _stream(stream)))
@@ -340,7 +373,7 @@ class Plan:
         """Run prepared ``IrfFrame`` descriptors (see :meth:`frames`)."""
         if self._ptr is None:
             raise RuntimeError("plan is closed")
-        cp = None if flagged_counts is None else flagged_counts.data_ptr()
+        cp = _counts(flagged_counts, n, "flagged_counts")
         _check("ir_filter_run_batch", self._lib.ir_filter_run_batch(self._ptr, arr, n, cp, _stream(stream)))
 
     def close(self) -> None:

@@ -119,6 +119,11 @@ class Server:
     def arena_used(self) -> int:
         return self._lib.ir_filter_server_arena_used(self._ptr)
 
+    @property
+    def resident_bytes(self) -> int:
+        """Device frame memory held: the arena plus every stream's resident slots."""
+        return self._lib.ir_filter_server_resident_bytes(self._ptr)
+
     def _flush(self) -> None:
         if self._offset is None:
             self._offset = self._lib.ir_filter_server_now(self._ptr)

@@ -80,6 +80,8 @@ def run(lib, src=SRC, sp=640, dst=DST, dp=640, W=320, H=240, dt=1, k=3, passes=1
     (dict(passes=2, scr=SRC + 5, xp=640), -7), (dict(passes=2, scr=DST, xp=640), -7),
     (dict(passes=2, scr=SCR, xp=10), -3),
     (dict(cnt=SRC + 8), -7),
+    (dict(passes=2, scr=SCR, xp=640, cnt=SCR + 640 * 100), -7),  # counts inside scratch
+    (dict(passes=2, scr=SCR, xp=640, cnt=SCR - 8), -7),  # second count is scratch's first byte
 ])
 def test_run_validation(lib, kw, want):
     assert run(lib, **kw) == want
@@ -164,3 +166,9 @@ def test_frame_tile_count(lib):
     assert lib.ir_filter_frame_tiles(129, 65) == 2 * 3
     assert lib.ir_filter_frame_tiles(1, 1) == 1
     assert lib.ir_filter_frame_tiles(0, 5) == 0
+
+
+def test_counts_just_outside_scratch_pass_validation(lib):
+    # the two counts end right before scratch: validation passes the alias
+    # check and fails on the next one (a pass count of 17)
+    assert run(lib, passes=17, scr=SCR, xp=640, cnt=SCR - 16) == -6

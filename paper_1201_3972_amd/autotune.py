@@ -157,10 +157,11 @@ def _same(torch, x, y) -> bool:
 # ----------------------------------------------------------------------------
 
 def tune_single(torch, dtype: str, windows: Sequence[int] = WINDOWS, frames: int = 256, rounds: int = 3,
-                reps: int = 5, pool=None, log: Callable[[str], None] = lambda m: None) -> Dict[str, dict]:
+                reps: int = 5, pool=None, stack=None, log: Callable[[str], None] = lambda m: None) -> Dict[str, dict]:
     """Best (threads, select) per window for ``ir_filter_run_frames`` on a
-    ``frames``-frame stack of ``pool`` (default: :func:`default_frames`)."""
-    src = _stack(torch, pool or default_frames(dtype), frames)
+    ``frames``-frame stack of ``pool`` (default: :func:`default_frames`), or on
+    a device-resident ``stack`` given by the caller."""
+    src = stack if stack is not None else _stack(torch, pool or default_frames(dtype), frames)
     dst = torch.empty_like(src)
     ref = torch.empty_like(src)
     out = {}

@@ -138,6 +138,23 @@ irf_status ir_filter_run(const void *src, size_t src_pitch, void *dst, size_t ds
                          size_t scratch_pitch, uint64_t *flagged_count, hipStream_t stream);
 
 /*
+ * ir_filter_run_noalloc -- ir_filter_run for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same results and counts, with the intermediate frame of
+ * passes >= 2 taken from a 32 MiB device array the library holds on each GPU
+ * (declared statically, looked up once per device; nothing is allocated or
+ * freed per call).  Limit: for passes >= 2, height * round_up(width * bytes
+ * per pixel, 256) must not exceed 32 MiB (IRF_ERR_CAPACITY otherwise, checked
+ * before any HIP call), e.g. 4096 x 4096 u16.  All calls on one GPU share the
+ * array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.  Other arguments as for
+ * ir_filter_run.
+ */
+irf_status ir_filter_run_noalloc(const void *src, size_t src_pitch, void *dst, size_t dst_pitch, int width,
+                                 int height, irf_dtype dtype, int window, int passes, uint64_t *flagged_count,
+                                 hipStream_t stream);
+
+/*
  * ir_filter_run_frames -- ir_filter_run over a stack of `nframes` frames of the
  * same size, one launch per pass (or per fused pair of passes, as for
  * ir_filter_run).  Frame i starts at src + i*src_stride (bytes),

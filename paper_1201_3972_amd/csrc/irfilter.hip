@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <mutex>
 
 #include "../../include/irfilter.h"
 #include "fnr_device.hpp"
@@ -169,6 +170,49 @@ irf_status run_frames(const void *src, size_t src_pitch, size_t src_stride, void
     return IRF_OK;
 }
 
+// ir_filter_run_noalloc: the intermediate passes of a call live in this
+// file-scope device array instead of a caller's scratch frame.  Every GPU the
+// library runs on holds its own copy until the process ends; all calls on one
+// GPU share it, so calls that overlap on one GPU race.  In host code the
+// array's name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+namespace noalloc {
+
+constexpr size_t kScratchBytes = (size_t)32 << 20;  // one 4096 x 4096 u16 frame
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_mu;
+void *g_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+// Address of this device's `scratch`, looked up with the device current on
+// the first call that needs it.
+irf_status device_scratch(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return IRF_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return IRF_ERR_HIP;
+        }
+        g_ptr[dev] = p;
+    }
+    *out = g_ptr[dev];
+    return IRF_OK;
+}
+
+// Row pitch of the intermediate frames: whole 256-byte lines.
+size_t scratch_pitch(int width, irf_dtype dtype) {
+    return ((size_t)width * (size_t)bytes_of(dtype) + 255) / 256 * 256;
+}
+
+}  // namespace noalloc
+
 }  // namespace
 }  // namespace irf
 
@@ -283,6 +327,25 @@ irf_status ir_filter_run(const void *src, size_t src_pitch, void *dst, size_t ds
     try {
         return run_frames(src, src_pitch, 0, dst, dst_pitch, 0, width, height, 1, dtype, window,
                           passes, scratch, scratch_pitch, 0, flagged_count, stream);
+    } catch (...) {
+        return IRF_ERR_HIP;
+    }
+}
+
+irf_status ir_filter_run_noalloc(const void *src, size_t src_pitch, void *dst, size_t dst_pitch, int width,
+                                 int height, irf_dtype dtype, int window, int passes, uint64_t *flagged_count,
+                                 hipStream_t stream) {
+    try {
+        if (!src || !dst) return IRF_ERR_NULL;
+        irf_status st = check_common(width, height, 1, dtype, window);
+        if (st) return st;
+        if (passes < 1 || passes > IRF_MAX_PASSES) return IRF_ERR_PASSES;
+        const size_t pitch = noalloc::scratch_pitch(width, dtype);
+        if (passes >= 2 && pitch * (size_t)height > noalloc::kScratchBytes) return IRF_ERR_CAPACITY;
+        void *scr = nullptr;
+        if (passes >= 2 && (st = noalloc::device_scratch(&scr))) return st;
+        return run_frames(src, src_pitch, 0, dst, dst_pitch, 0, width, height, 1, dtype, window, passes, scr,
+                          pitch, 0, flagged_count, stream);
     } catch (...) {
         return IRF_ERR_HIP;
     }

@@ -37,6 +37,7 @@ SIGNATURES = {
     "ir_filter_detect_directional": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _vp, _vp]),
     "ir_filter_median": (_i32, [_vp, _sz, _vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _vp]),
     "ir_filter_run": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _i32, _vp, _sz, _vp, _vp]),
+    "ir_filter_run_noalloc": (_i32, [_vp, _sz, _vp, _sz, _i32, _i32, _i32, _i32, _i32, _vp, _vp]),
     "ir_filter_run_frames": (_i32, [_vp, _sz, _sz, _vp, _sz, _sz, _i32, _i32, _i32, _i32, _i32, _i32,
                                     _vp, _sz, _sz, _vp, _vp]),
     "ir_filter_plan_create": (_i32, [ctypes.POINTER(ctypes.c_void_p), _i32, _i32, ctypes.c_uint]),
@@ -255,6 +256,19 @@ def ir_filter_run(src, dst, window: int, passes: int = 1, scratch=None, flagged_
     cp = _counts(flagged_count, passes)
     _check("ir_filter_run", load().ir_filter_run(sp, spitch, dp, dpitch, W, H, _dtype_code(src), window,
                                                  passes, xp, xpitch, cp, _stream(stream)))
+
+
+def ir_filter_run_noalloc(src, dst, window: int, passes: int = 1, flagged_count=None, stream=None) -> None:
+    """``ir_filter_run`` whose intermediate passes use the library's own
+    per-GPU device array (no scratch argument, nothing allocated per call);
+    calls that overlap on one GPU share that array and race."""
+    _same(src, dst, "dst")
+    sp, spitch = _frame(src, "src")
+    dp, dpitch = _frame(dst, "dst")
+    H, W = src.shape
+    cp = _counts(flagged_count, passes)
+    _check("ir_filter_run_noalloc", load().ir_filter_run_noalloc(sp, spitch, dp, dpitch, W, H, _dtype_code(src),
+                                                                 window, passes, cp, _stream(stream)))
 
 
 def ir_filter_run_frames(src, dst, window: int, passes: int = 1, scratch=None, flagged_count=None,

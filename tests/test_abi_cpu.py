@@ -172,3 +172,14 @@ def test_counts_just_outside_scratch_pass_validation(lib):
     # the two counts end right before scratch: validation passes the alias
     # check and fails on the next one (a pass count of 17)
     assert run(lib, passes=17, scr=SCR, xp=640, cnt=SCR - 16) == -6
+
+
+def test_noalloc_rejects_frames_beyond_its_array_before_any_device_call(lib):
+    f = lib.ir_filter_run_noalloc
+    # 4096 x 4096 u16 fills the 32 MiB array exactly; one more row does not fit
+    assert f(SRC, 8192, DST, 8192, 4096, 4097, 2, 3, 2, None, None) == -10
+    assert f(SRC, 8192, DST, 8192, 32768, 32768, 2, 3, 3, None, None) == -10
+    assert f(None, 8192, DST, 8192, 64, 64, 2, 3, 2, None, None) == -1
+    assert f(SRC, 8192, DST, 8192, 64, 64, 2, 4, 2, None, None) == -5
+    assert f(SRC, 8192, DST, 8192, 64, 64, 2, 3, 0, None, None) == -6
+    assert f(SRC, 8192, DST, 8192, 64, 64, 2, 3, 17, None, None) == -6

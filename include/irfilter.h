@@ -60,8 +60,7 @@ typedef enum {
     IRF_ERR_PITCH = -3,   /* a pitch is smaller than one row or not below 2^24, a frame spans
                              4 GiB or more, or a stride is smaller than one frame */
     IRF_ERR_DTYPE = -4,   /* pixel type is not IRF_U8 or IRF_U16 */
-    IRF_ERR_WINDOW = -5,  /* window is not odd or outside 3..IRF_MAX_WINDOW (3..IRF_MAX_BATCH_WINDOW
-                             for batches and the server) */
+    IRF_ERR_WINDOW = -5,  /* window is not odd or outside 3..IRF_MAX_WINDOW */
     IRF_ERR_PASSES = -6,  /* passes outside 1..IRF_MAX_PASSES, or scratch missing for passes >= 2 */
     IRF_ERR_ALIAS = -7,   /* an output overlaps an input or another output */
     IRF_ERR_HIP = -8,     /* a HIP call failed (the HIP error is cleared) */
@@ -71,10 +70,10 @@ typedef enum {
 } irf_status;
 
 #define IRF_MAX_DIM 32768
-/* Single-size entry points take windows up to 31x31; batch plans and the
- * server up to 15x15. */
+/* Every entry point takes windows up to 31x31 (batch plans and the server
+ * included). */
 #define IRF_MAX_WINDOW 31
-#define IRF_MAX_BATCH_WINDOW 15
+#define IRF_MAX_BATCH_WINDOW 31
 #define IRF_MAX_PASSES 16
 
 /*
@@ -174,9 +173,12 @@ irf_status ir_filter_run_frames(const void *src, size_t src_pitch, size_t src_st
  * irf_frame describes one frame: device src/dst, pitches, size, pixel type and
  * window; frames of a batch are independent and may all differ.  Every frame
  * is filtered once with the FNR filter (same result as ir_filter_run with
- * passes = 1).  Frames with windows 3..7 share one persistent kernel, frames
- * with windows 9..11 a second and frames with windows 13..15 a third, launched
- * one after the other on the same stream.
+ * passes = 1).  Frames with windows 3..9 share one persistent kernel, frames
+ * with windows 11..15 a second, and each window above 15x15 has a kernel of
+ * its own; a batch launches the kernels of the windows it holds, one after the
+ * other on the same stream (a batch of windows 3..9 is one launch).  With
+ * IRF_PLAN_GRAPH the launches are replayed from a graph captured per set of
+ * kernels on its first use.
  */
 typedef struct {
     const void *src;

@@ -15,9 +15,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_PATH = os.path.join(PKG, "libirfilter.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = [os.path.join(CSRC, n) for n in ("stack_u16.hip", "stack_u8.hip", "stack_large_u16.hip",
-                                          "stack_large_u8.hip", "batch.hip", "irfilter.hip", "server.hip",
-                                          "fused.hip")]
+SOURCES = [os.path.join(CSRC, n) for n in ("batch_cl_a.hip", "batch_cl_b.hip", "stack_u16.hip", "stack_u8.hip",
+                                          "stack_large_u16.hip", "stack_large_u8.hip", "batch_c0.hip",
+                                          "batch_c1.hip", "batch.hip", "irfilter.hip", "server.hip", "fused.hip")]
 ARCH = os.environ.get("IRF_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

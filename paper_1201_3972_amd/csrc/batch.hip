@@ -8,11 +8,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
 #include <vector>
 
 #include "../../include/irfilter.h"
-#include "batch_device.hpp"
+#include "batch_kernels.hpp"
 #include "host_common.hpp"
 
 using namespace irf;
@@ -20,9 +21,8 @@ using namespace irf::host;
 
 namespace {
 
-constexpr int kSets = 2;          // device table sets used alternately
-constexpr size_t kQueueBytes = 64;  // one BatchQueue record per class, padded
-static_assert(kBatchClasses * sizeof(BatchQueue) <= kQueueBytes, "queue records overflow");
+constexpr int kSets = 2;  // device table sets used alternately
+constexpr size_t kQueueBytes = (kBatchClasses * sizeof(BatchQueue) + 255) / 256 * 256;  // queue records, padded
 
 // Workgroup size of plans created from now on (0 = the default, 128 threads).
 std::atomic<int> g_batch_threads{0};
@@ -37,22 +37,42 @@ int frame_tiles(int width, int height, int threads) {
     return ((width + kTileW - 1) / kTileW) * ((height + th - 1) / th);
 }
 
-template <int CLASS, int NT>
-int batch_grid() {
-    static const int per_cu = [] {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fnr_batch_kernel<CLASS, NT>, NT, 0) !=
-                hipSuccess ||
-            n < 1)
-            n = 1;
-        return n;
-    }();
-    return per_cu * device_cus();
+int class_blocks_per_cu(int c, int threads) {
+    switch (c) {
+        case 0: return BatchClass<0>::blocks_per_cu(threads);
+        case 1: return BatchClass<1>::blocks_per_cu(threads);
+        case 2: return BatchClass<2>::blocks_per_cu(threads);
+        case 3: return BatchClass<3>::blocks_per_cu(threads);
+        case 4: return BatchClass<4>::blocks_per_cu(threads);
+        case 5: return BatchClass<5>::blocks_per_cu(threads);
+        case 6: return BatchClass<6>::blocks_per_cu(threads);
+        case 7: return BatchClass<7>::blocks_per_cu(threads);
+        case 8: return BatchClass<8>::blocks_per_cu(threads);
+        default: return BatchClass<9>::blocks_per_cu(threads);
+    }
+}
+
+void class_launch(int c, int threads, int grid, const FrameDesc *d, const uint32_t *map, BatchQueue *q,
+                  hipStream_t s) {
+    static_assert(kBatchClasses == 10, "one case per class");
+    switch (c) {
+        case 0: BatchClass<0>::launch(threads, grid, d, map, q, s); break;
+        case 1: BatchClass<1>::launch(threads, grid, d, map, q, s); break;
+        case 2: BatchClass<2>::launch(threads, grid, d, map, q, s); break;
+        case 3: BatchClass<3>::launch(threads, grid, d, map, q, s); break;
+        case 4: BatchClass<4>::launch(threads, grid, d, map, q, s); break;
+        case 5: BatchClass<5>::launch(threads, grid, d, map, q, s); break;
+        case 6: BatchClass<6>::launch(threads, grid, d, map, q, s); break;
+        case 7: BatchClass<7>::launch(threads, grid, d, map, q, s); break;
+        case 8: BatchClass<8>::launch(threads, grid, d, map, q, s); break;
+        default: BatchClass<9>::launch(threads, grid, d, map, q, s); break;
+    }
 }
 
 }  // namespace
 
-// Device layout of one table set: [queues (64 B) | descriptors | tile map].
+// Device layout of one table set: [queues | descriptors | tile map].  The map
+// holds every tile of a batch, class by class; queue c covers class c's part.
 struct irf_plan {
     int max_frames = 0, max_tiles = 0;
     unsigned flags = 0;
@@ -60,51 +80,64 @@ struct irf_plan {
     int threads = kThreads;  // workgroup size of the batch kernels (tile height / 8 * 32)
     int grid[kBatchClasses] = {};
     int next_set = 0;
+    hipStream_t capture = nullptr;  // graph capture stream (IRF_PLAN_GRAPH)
     struct Set {
         unsigned char *dev = nullptr;
         unsigned char *host = nullptr;  // pinned staging
         hipEvent_t copied = nullptr;    // staging may be rewritten
         hipEvent_t done = nullptr;      // device tables may be rewritten
-        hipGraphExec_t graph = nullptr;
+        std::map<unsigned, hipGraphExec_t> graphs;  // by the set of classes a batch uses
         bool used = false;
     } set[kSets];
 };
 
 namespace {
 
-// Each window class has its own queue and its own region of the tile map
-// (class c at map + c * max_tiles), so the arguments of every kernel are fixed
-// per table set and can be captured in a graph once.  `classes` selects the
-// kernels (bit c = class c).
-template <int CLASS>
-void launch_class(const irf_plan *p, const irf_plan::Set &s, hipStream_t stream) {
+// The kernels of the classes in `classes` (bit c = class c), one after the
+// other; the arguments are fixed per table set, so a launch sequence can be
+// captured in a graph once and replayed for every batch using those classes.
+void launch_batch(const irf_plan *p, const irf_plan::Set &s, unsigned classes, hipStream_t stream) {
     BatchQueue *q = reinterpret_cast<BatchQueue *>(s.dev);
     const FrameDesc *d = reinterpret_cast<const FrameDesc *>(s.dev + p->desc_off);
-    const uint32_t *map = reinterpret_cast<const uint32_t *>(s.dev + p->map_off) + (size_t)CLASS * p->max_tiles;
-    if (p->threads == 256)
-        hipLaunchKernelGGL((fnr_batch_kernel<CLASS, 256>), dim3(p->grid[CLASS]), dim3(256), 0, stream, d, map,
-                           q + CLASS, 0x00010001u);
-    else
-        hipLaunchKernelGGL((fnr_batch_kernel<CLASS, 128>), dim3(p->grid[CLASS]), dim3(128), 0, stream, d, map,
-                           q + CLASS, 0x00010001u);
+    const uint32_t *map = reinterpret_cast<const uint32_t *>(s.dev + p->map_off);
+    for (int c = 0; c < kBatchClasses; ++c)
+        if (classes & (1u << c)) class_launch(c, p->threads, p->grid[c], d, map, q + c, stream);
 }
 
-void launch_batch(const irf_plan *p, const irf_plan::Set &s, unsigned classes, hipStream_t stream) {
-    static_assert(kBatchClasses == 3, "one launch per class");
-    if (classes & 1u) launch_class<0>(p, s, stream);
-    if (classes & 2u) launch_class<1>(p, s, stream);
-    if (classes & 4u) launch_class<2>(p, s, stream);
+// The graph of this set and class set, captured on first use.
+irf_status set_graph(irf_plan *p, irf_plan::Set &s, unsigned classes, hipGraphExec_t *out) {
+    auto it = s.graphs.find(classes);
+    if (it != s.graphs.end()) {
+        *out = it->second;
+        return IRF_OK;
+    }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    bool ok = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) launch_batch(p, s, classes, p->capture);
+    ok = (hipStreamEndCapture(p->capture, &g) == hipSuccess) && ok;
+    ok = ok && hipGraphInstantiate(&e, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok) {
+        if (e) (void)hipGraphExecDestroy(e);
+        (void)hipGetLastError();
+        return IRF_ERR_HIP;
+    }
+    s.graphs[classes] = e;
+    *out = e;
+    return IRF_OK;
 }
 
 void free_plan(irf_plan *p) {
     if (!p) return;
     for (auto &s : p->set) {
-        if (s.graph) (void)hipGraphExecDestroy(s.graph);
+        for (auto &kv : s.graphs) (void)hipGraphExecDestroy(kv.second);
         if (s.copied) (void)hipEventDestroy(s.copied);
         if (s.done) (void)hipEventDestroy(s.done);
         if (s.dev) (void)hipFree(s.dev);
         if (s.host) (void)hipHostFree(s.host);
     }
+    if (p->capture) (void)hipStreamDestroy(p->capture);
     delete p;
 }
 
@@ -168,18 +201,10 @@ irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles,
         p->flags = flags;
         p->desc_off = kQueueBytes;
         p->map_off = p->desc_off + sizeof(FrameDesc) * (size_t)max_frames;
-        p->bytes = p->map_off + sizeof(uint32_t) * kBatchClasses * (size_t)max_tiles;
+        p->bytes = p->map_off + sizeof(uint32_t) * (size_t)max_tiles;
         (void)hipGetLastError();
         p->threads = batch_threads_now();
-        if (p->threads == 256) {
-            p->grid[0] = batch_grid<0, 256>();
-            p->grid[1] = batch_grid<1, 256>();
-            p->grid[2] = batch_grid<2, 256>();
-        } else {
-            p->grid[0] = batch_grid<0, 128>();
-            p->grid[1] = batch_grid<1, 128>();
-            p->grid[2] = batch_grid<2, 128>();
-        }
+        for (int c = 0; c < kBatchClasses; ++c) p->grid[c] = class_blocks_per_cu(c, p->threads) * device_cus();
         for (auto &s : p->set) {
             if (hipMalloc(&s.dev, p->bytes) != hipSuccess) {
                 free_plan(p);
@@ -199,24 +224,11 @@ irf_status ir_filter_plan_create(irf_plan **plan, int max_frames, int max_tiles,
             }
         }
         if (flags & IRF_PLAN_GRAPH) {
-            hipStream_t cs = nullptr;
-            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
-                free_plan(p);
-                (void)hipGetLastError();
-                return IRF_ERR_HIP;
-            }
-            bool ok = true;
-            for (auto &s : p->set) {
-                hipGraph_t g = nullptr;
-                ok = ok && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-                if (ok) launch_batch(p, s, (1u << kBatchClasses) - 1, cs);
-                ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && ok;
-                ok = ok && hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0) == hipSuccess;
-                if (g) (void)hipGraphDestroy(g);
-                if (!ok) break;
-            }
-            (void)hipStreamDestroy(cs);
-            if (!ok) {
+            // graphs are captured per set of classes on first use; the class of
+            // windows 3..9, which video mixes use, is captured now
+            hipGraphExec_t e = nullptr;
+            if (hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) != hipSuccess ||
+                set_graph(p, p->set[0], 1u, &e) || set_graph(p, p->set[1], 1u, &e)) {
                 free_plan(p);
                 (void)hipGetLastError();
                 return IRF_ERR_HIP;
@@ -247,8 +259,9 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
             if ((st = check_layout(f.dst_pitch, 0, f.width, f.height, 1, b))) return st;
             tiles[batch_class(f.window)] += frame_tiles(f.width, f.height, p->threads);
         }
-        for (int c = 0; c < kBatchClasses; ++c)
-            if (tiles[c] > p->max_tiles) return IRF_ERR_CAPACITY;
+        long long all_tiles = 0;
+        for (int c = 0; c < kBatchClasses; ++c) all_tiles += tiles[c];
+        if (all_tiles > p->max_tiles) return IRF_ERR_CAPACITY;
         if (batch_aliases(frames, n)) return IRF_ERR_ALIAS;
         if (counts) {
             const Span cs = {reinterpret_cast<uintptr_t>(counts),
@@ -273,8 +286,13 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         FrameDesc *d = reinterpret_cast<FrameDesc *>(s.host + p->desc_off);
         uint32_t *map = reinterpret_cast<uint32_t *>(s.host + p->map_off);
         memset(q, 0, kQueueBytes);
-        for (int c = 0; c < kBatchClasses; ++c) q[c].total = (unsigned)tiles[c];
-        int begin[kBatchClasses] = {};
+        int begin[kBatchClasses] = {};  // class c's tiles fill map[base_c, base_c + tiles[c])
+        unsigned base = 0;
+        for (int c = 0; c < kBatchClasses; ++c) {
+            q[c].total = (unsigned)tiles[c];
+            q[c].base = base;
+            base += (unsigned)tiles[c];
+        }
         for (int i = 0; i < n; ++i) {
             const irf_frame &f = frames[i];
             const int b = bytes_of(f.dtype), c = batch_class(f.window), nt = frame_tiles(f.width, f.height, p->threads);
@@ -292,7 +310,7 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
             e.kind = batch_kind(b, f.window);
             e.aligned = is16(f.src) && is16(f.dst) && is16(f.src_pitch) && is16(f.dst_pitch);
             e.pad = 0;
-            uint32_t *m = map + (size_t)c * p->max_tiles + begin[c];
+            uint32_t *m = map + q[c].base + begin[c];
             for (int t = 0; t < nt; ++t) m[t] = (uint32_t)i;
             begin[c] += nt;
         }
@@ -302,25 +320,24 @@ irf_status ir_filter_run_batch(irf_plan *p, const irf_frame *frames, int n, uint
         if (hipMemcpyAsync(s.dev, s.host, p->desc_off + sizeof(FrameDesc) * (size_t)n,
                            hipMemcpyHostToDevice, stream) != hipSuccess)
             return IRF_ERR_HIP;
-        for (int c = 0; c < kBatchClasses; ++c) {
-            if (tiles[c] == 0) continue;
-            const size_t off = p->map_off + sizeof(uint32_t) * (size_t)c * p->max_tiles;
-            if (hipMemcpyAsync(s.dev + off, s.host + off, sizeof(uint32_t) * (size_t)tiles[c],
-                               hipMemcpyHostToDevice, stream) != hipSuccess)
-                return IRF_ERR_HIP;
-        }
+        if (hipMemcpyAsync(s.dev + p->map_off, s.host + p->map_off, sizeof(uint32_t) * (size_t)all_tiles,
+                           hipMemcpyHostToDevice, stream) != hipSuccess)
+            return IRF_ERR_HIP;
         if (hipEventRecord(s.copied, stream) != hipSuccess) return IRF_ERR_HIP;
         s.used = true;
         if (counts) {
             hipLaunchKernelGGL(zero_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, stream,
                                reinterpret_cast<unsigned long long *>(counts), n);
         }
-        if (s.graph) {
-            if (hipGraphLaunch(s.graph, stream) != hipSuccess) return IRF_ERR_HIP;
+        unsigned classes = 0;
+        for (int c = 0; c < kBatchClasses; ++c)
+            if (tiles[c]) classes |= 1u << c;
+        if (p->flags & IRF_PLAN_GRAPH) {
+            hipGraphExec_t g = nullptr;
+            irf_status st = set_graph(p, s, classes, &g);
+            if (st) return st;
+            if (hipGraphLaunch(g, stream) != hipSuccess) return IRF_ERR_HIP;
         } else {
-            unsigned classes = 0;
-            for (int c = 0; c < kBatchClasses; ++c)
-                if (tiles[c]) classes |= 1u << c;
             launch_batch(p, s, classes, stream);
         }
         if (hipEventRecord(s.done, stream) != hipSuccess) return IRF_ERR_HIP;

@@ -1,8 +1,9 @@
 // batch_device.hpp -- one persistent launch over a batch of frames of uneven
 // size, pixel type and window (the FNR filter of fnr_device.hpp, one pass).
 //
-// The host lists every frame's tiles in one index space and uploads, per
-// batch: a descriptor per frame, a tile -> frame map and a queue {next, total}.
+// The host lists every frame's tiles in one index space per window class and
+// uploads, per batch: a descriptor per frame, a tile -> frame map and a queue
+// {next, total, base} per class.
 // Workgroups take tiles from the queue with one atomic each; the atomic for the
 // next tile is issued before the current tile's loads, so its latency hides
 // behind them.  Per tile the workgroup switches (uniformly) to the device code
@@ -31,23 +32,29 @@ struct FrameDesc {
 struct BatchQueue {
     unsigned int next;   // next tile to hand out
     unsigned int total;  // tiles in the class
-    unsigned int pad[2];
+    unsigned int base;   // the class's first entry in the tile -> frame map
+    unsigned int pad;
 };
 
-// Window classes, one kernel each: 3..7, 9..11 and 13..15 (LDS and registers
-// sized for the class's largest window).
-constexpr int kBatchClasses = 3;
-constexpr int kBatchClassMax[kBatchClasses] = {7, 11, 15};
+// Window classes, one kernel each: 3..9 (selection networks; 4 waves per SIMD),
+// 11..15 (networks; 2 waves), and one class per window above 15x15 (group
+// bisection; their code does not share one kernel without spilling).  LDS and
+// registers are sized for the class's largest window, so a batch whose windows
+// all lie in one class (the usual video mixes of 3..9) runs as one persistent
+// launch.
+constexpr int kBatchClasses = 10;
+constexpr int kBatchClassMin[kBatchClasses] = {3, 11, 17, 19, 21, 23, 25, 27, 29, 31};
+constexpr int kBatchClassMax[kBatchClasses] = {9, 15, 17, 19, 21, 23, 25, 27, 29, 31};
 // Occupancy targets: every window's code sits in its class's kernel, whose
 // register count is the worst case over them; these targets keep each kernel at
 // the occupancy of its largest window's own kernel without spilling.
-constexpr int kBatchClassWaves[kBatchClasses] = {4, 3, 2};
+constexpr int kBatchClassWaves[kBatchClasses] = {4, 2, 2, 2, 2, 2, 2, 2, 2, 2};
 
 __host__ __device__ constexpr int batch_kind(int bytes, int window) {
-    return (bytes == 1 ? 0 : 8) + (window - 3) / 2;
+    return (bytes == 1 ? 0 : 16) + (window - 3) / 2;
 }
 __host__ __device__ constexpr int batch_class(int window) {
-    return window <= kBatchClassMax[0] ? 0 : (window <= kBatchClassMax[1] ? 1 : 2);
+    return window <= kBatchClassMax[0] ? 0 : (window <= kBatchClassMax[1] ? 1 : 2 + (window - 17) / 2);
 }
 
 // One tile of the queue, with the stack kernel's issue order: the tile's global
@@ -81,6 +88,24 @@ __device__ __forceinline__ uint32_t batch_tile(const FrameDesc &d, int local, un
     return process_tile<T, K, MODE_FNR, NT, default_select(K), true>(a, local, sm);
 }
 
+// The tile's device code by (pixel type, window) among the class's windows:
+// a uniform branch over the kinds, each an inlined filter body.
+template <int CLASS, int NT, int K = kBatchClassMin[CLASS]>
+__device__ __forceinline__ uint32_t batch_dispatch(const FrameDesc &d, int local, unsigned char *smem,
+                                                   uint32_t ticket, unsigned int *slot, uint32_t pk_one) {
+    if constexpr (K > kBatchClassMax[CLASS]) {
+        // no such kind (the host admits only windows of the class): hand the
+        // next ticket on so the loop still advances
+        if (threadIdx.x == 0) *slot = ticket;
+        __syncthreads();
+        return 0;
+    } else {
+        if (d.kind == batch_kind(1, K)) return batch_tile<uint8_t, K, NT>(d, local, smem, ticket, slot, pk_one);
+        if (d.kind == batch_kind(2, K)) return batch_tile<uint16_t, K, NT>(d, local, smem, ticket, slot, pk_one);
+        return batch_dispatch<CLASS, NT, K + 2>(d, local, smem, ticket, slot, pk_one);
+    }
+}
+
 template <int CLASS, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kBatchClassWaves[CLASS], 8))) void fnr_batch_kernel(const FrameDesc *descs,
                                                              const uint32_t *tile_frame,
@@ -93,6 +118,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kBatchClassW
     // (iteration i+2) lies behind the barriers of iteration i+1
     __shared__ unsigned int s_next[2];
     const unsigned int total = queue->total;
+    tile_frame += queue->base;
     if (threadIdx.x == 0) s_next[0] = atomicAdd(&queue->next, 1u);
     __syncthreads();
     unsigned int t = s_next[0];
@@ -103,31 +129,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(kBatchClassW
         const int local = (int)t - d.tile_begin;
         uint32_t ticket = 0;
         if (threadIdx.x == 0) ticket = atomicAdd(&queue->next, 1u);
-        uint32_t flagged = 0;
-        if constexpr (CLASS == 0) {
-            switch (d.kind) {
-                case batch_kind(1, 3): flagged = batch_tile<uint8_t, 3, NT>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 5): flagged = batch_tile<uint8_t, 5, NT>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 7): flagged = batch_tile<uint8_t, 7, NT>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 3): flagged = batch_tile<uint16_t, 3, NT>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 5): flagged = batch_tile<uint16_t, 5, NT>(d, local, smem, ticket, slot, pk_one); break;
-                default: flagged = batch_tile<uint16_t, 7, NT>(d, local, smem, ticket, slot, pk_one); break;
-            }
-        } else if constexpr (CLASS == 1) {
-            switch (d.kind) {
-                case batch_kind(1, 9): flagged = batch_tile<uint8_t, 9, NT>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 11): flagged = batch_tile<uint8_t, 11, NT>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 9): flagged = batch_tile<uint16_t, 9, NT>(d, local, smem, ticket, slot, pk_one); break;
-                default: flagged = batch_tile<uint16_t, 11, NT>(d, local, smem, ticket, slot, pk_one); break;
-            }
-        } else {
-            switch (d.kind) {
-                case batch_kind(1, 13): flagged = batch_tile<uint8_t, 13, NT>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(1, 15): flagged = batch_tile<uint8_t, 15, NT>(d, local, smem, ticket, slot, pk_one); break;
-                case batch_kind(2, 13): flagged = batch_tile<uint16_t, 13, NT>(d, local, smem, ticket, slot, pk_one); break;
-                default: flagged = batch_tile<uint16_t, 15, NT>(d, local, smem, ticket, slot, pk_one); break;
-            }
-        }
+        const uint32_t flagged = batch_dispatch<CLASS, NT>(d, local, smem, ticket, slot, pk_one);
         if (d.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)
             atomicAdd(d.count, (unsigned long long)flagged);
         t = *slot;  // the barrier inside the next load_tile frees this tile's LDS

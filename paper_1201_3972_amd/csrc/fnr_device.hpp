@@ -254,19 +254,37 @@ __device__ __forceinline__ uint4 load_inside(__amdgpu_buffer_rsrc_t rs, uint32_t
 // thread's global loads are issued and before its LDS writes, so the wait at
 // the barrier overlaps the loads' latency; the loads are issued at the highest
 // wave priority.
-template <typename T, int K, int NT = kThreads, bool HALF = false, bool EARLY = false>
-__device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
-                                          int y0, bool aligned, uint16_t *tile) {
+// The chunks of one tile held in registers between their loads and their LDS
+// writes, and the geometry of the load rounds.
+template <int K, int NT>
+struct TileChunks {
     using G = Geometry<K, NT>;
-    constexpr int kStep = NT / 16;
-    constexpr int kRounds = (G::rows + kStep - 1) / kStep;
-    constexpr int HC = G::halo / 8;                    // halo chunks on each side
-    constexpr int kHalos = 2 * HC * G::rows;           // halo chunks of the tile
-    constexpr int kHRounds = (kHalos + NT - 1) / NT;
-    constexpr int kHStep = NT / (2 * HC);              // halo rows per round
-    constexpr int kHWave = 64 / (2 * HC);              // halo rows of a wave in a round
-    constexpr uint32_t b = sizeof(T);
+    static constexpr int kStep = NT / 16;
+    static constexpr int kRounds = (G::rows + kStep - 1) / kStep;
+    static constexpr int HC = G::halo / 8;                    // halo chunks on each side
+    static constexpr int kHalos = 2 * HC * G::rows;           // halo chunks of the tile
+    static constexpr int kHRounds = (kHalos + NT - 1) / NT;
+    static constexpr int kHStep = NT / (2 * HC);              // halo rows per round
+    static constexpr int kHWave = 64 / (2 * HC);              // halo rows of a wave in a round
     static_assert(kTileW == 16 * 8 && G::chunks == 16 + 2 * HC, "16 interior chunks per row");
+    uint4 v[kRounds], h[kHRounds];
+};
+
+// The thread's halo chunk column (fixed for the whole kernel).
+template <int K, int NT>
+__device__ __forceinline__ int halo_column(int tid) {
+    using C = TileChunks<K, NT>;
+    const int which = tid % (2 * C::HC);
+    return C::HC == 1 ? (which ? Geometry<K, NT>::chunks - 1 : 0) : (which < C::HC ? which : 16 + which);
+}
+
+// Issue the global loads of the tile at (x0, y0) into registers.
+template <typename T, int K, int NT, bool HALF>
+__device__ __forceinline__ void issue_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0, int y0,
+                                           bool aligned, TileChunks<K, NT> &c) {
+    using G = Geometry<K, NT>;
+    using C = TileChunks<K, NT>;
+    constexpr uint32_t b = sizeof(T);
     const int tid = threadIdx.x;
     const int cx = tid & 15, row0 = tid >> 4;
     const int ytop = y0 - G::r;
@@ -275,61 +293,79 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
     // wave-uniform: the wave's first interior and halo row within a round, and
     // whether the tile's interior and halo columns lie inside the frame
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wrow = wave * 4, whrow = wave * kHWave;
+    const int wrow = wave * 4, whrow = wave * C::kHWave;
     const bool in_x = aligned && x0 >= 0 && x0 + kTileW <= W;
     const bool in_xh = aligned && x0 - G::halo >= 0 && x0 + kTileW + G::halo <= W;
     // per thread: column and offset from the wave's first row
     const int gx = x0 + 8 * cx;
     const uint32_t voff = (uint32_t)(row0 & 3) * p32 + 8u * b * (uint32_t)cx;
-    const int which = tid % (2 * HC), hrow0 = tid / (2 * HC);
-    const int hcol = HC == 1 ? (which ? G::chunks - 1 : 0) : (which < HC ? which : 16 + which);
+    const int hrow0 = tid / (2 * C::HC);
+    const int hcol = halo_column<K, NT>(tid);
     const int gxh = x0 - G::halo + 8 * hcol;
     const uint32_t voffh = (uint32_t)(hrow0 - whrow) * p32 + 8u * b * (uint32_t)hcol;
-    uint4 v[kRounds], h[kHRounds];
-    if constexpr (EARLY) __builtin_amdgcn_s_setprio(3);
 #pragma unroll
-    for (int j = 0; j < kRounds; ++j) {
-        const int row = row0 + j * kStep;
-        const int first = ytop + j * kStep + wrow;  // the wave's rows: first .. first + 3
+    for (int j = 0; j < C::kRounds; ++j) {
+        const int row = row0 + j * C::kStep;
+        const int first = ytop + j * C::kStep + wrow;  // the wave's rows: first .. first + 3
         if (in_x && first >= 0 && first + 3 < H) {
-            if (j < kRounds - 1 || row < G::rows)
-                v[j] = load_inside<T, HALF>(rs, voff, (uint32_t)first * p32 + (uint32_t)x0 * b);
-        } else if (j < kRounds - 1 || row < G::rows) {
+            if (j < C::kRounds - 1 || row < G::rows)
+                c.v[j] = load_inside<T, HALF>(rs, voff, (uint32_t)first * p32 + (uint32_t)x0 * b);
+        } else if (j < C::kRounds - 1 || row < G::rows) {
             const int gy = min(max(ytop + row, 0), H - 1);
-            v[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, p32), gx, W, aligned);
+            c.v[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, p32), gx, W, aligned);
         }
     }
 #pragma unroll
-    for (int j = 0; j < kHRounds; ++j) {
+    for (int j = 0; j < C::kHRounds; ++j) {
         const int hc = tid + j * NT;
-        const int hrow = hrow0 + j * kHStep;
-        const int first = ytop + j * kHStep + whrow;  // the wave's halo rows: first .. first + kHWave - 1
-        if (in_xh && first >= 0 && first + kHWave - 1 < H) {
-            if (hc < kHalos)
-                h[j] = load_inside<T, HALF>(rs, voffh, (uint32_t)first * p32 + (uint32_t)(x0 - G::halo) * b);
-        } else if (hc < kHalos) {
+        const int hrow = hrow0 + j * C::kHStep;
+        const int first = ytop + j * C::kHStep + whrow;  // the wave's halo rows: first .. first + kHWave - 1
+        if (in_xh && first >= 0 && first + C::kHWave - 1 < H) {
+            if (hc < C::kHalos)
+                c.h[j] = load_inside<T, HALF>(rs, voffh, (uint32_t)first * p32 + (uint32_t)(x0 - G::halo) * b);
+        } else if (hc < C::kHalos) {
             const int gy = min(max(ytop + hrow, 0), H - 1);
-            h[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, p32), gxh, W, aligned);
+            c.h[j] = load_chunk<T, HALF>(src, __umul24((uint32_t)gy, p32), gxh, W, aligned);
         }
     }
+}
+
+// Write the chunks into the LDS tile.
+template <int K, int NT>
+__device__ __forceinline__ void commit_tile(const TileChunks<K, NT> &c, uint16_t *tile) {
+    using G = Geometry<K, NT>;
+    using C = TileChunks<K, NT>;
+    const int tid = threadIdx.x;
+    const int cx = tid & 15, row0 = tid >> 4;
+    const int hrow0 = tid / (2 * C::HC);
+    const int hcol = halo_column<K, NT>(tid);
+#pragma unroll
+    for (int j = 0; j < C::kRounds; ++j) {
+        const int row = row0 + j * C::kStep;
+        if (j < C::kRounds - 1 || row < G::rows)
+            *reinterpret_cast<uint4 *>(tile + row * G::pitch + 8 * (cx + C::HC)) = c.v[j];
+    }
+#pragma unroll
+    for (int j = 0; j < C::kHRounds; ++j) {
+        const int hc = tid + j * NT;
+        if (hc < C::kHalos) {
+            const int hrow = hrow0 + j * C::kHStep;
+            *reinterpret_cast<uint4 *>(tile + hrow * G::pitch + 8 * hcol) = c.h[j];
+        }
+    }
+}
+
+template <typename T, int K, int NT = kThreads, bool HALF = false, bool EARLY = false>
+__device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
+                                          int y0, bool aligned, uint16_t *tile) {
+    TileChunks<K, NT> c;
+    if constexpr (EARLY) __builtin_amdgcn_s_setprio(3);
+    issue_tile<T, K, NT, HALF>(src, pitch, W, H, x0, y0, aligned, c);
     if constexpr (EARLY) {
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
     }
-#pragma unroll
-    for (int j = 0; j < kRounds; ++j) {
-        const int row = row0 + j * kStep;
-        if (j < kRounds - 1 || row < G::rows)
-            *reinterpret_cast<uint4 *>(tile + row * G::pitch + 8 * (cx + HC)) = v[j];
-    }
-#pragma unroll
-    for (int j = 0; j < kHRounds; ++j) {
-        const int hc = tid + j * NT;
-        if (hc < kHalos) {
-            const int hrow = hrow0 + j * kHStep;
-            *reinterpret_cast<uint4 *>(tile + hrow * G::pitch + 8 * hcol) = h[j];
-        }
-    }
+    commit_tile<K, NT>(c, tile);
 }
 
 // ---------------------------------------------------------------------------

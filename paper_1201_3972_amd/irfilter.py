@@ -72,7 +72,7 @@ IRF_SELECT_BISECT = 2
 IRF_SELECT_GROUP = 3
 SELECT_NAMES = {IRF_SELECT_NETWORK: "network", IRF_SELECT_BISECT: "bisect", IRF_SELECT_GROUP: "group"}
 MAX_WINDOW = 31        # single-size entry points
-MAX_BATCH_WINDOW = 15  # batch plans and the server
+MAX_BATCH_WINDOW = 31  # batch plans and the server (every entry point: 3..31)
 
 
 IRF_PLAN_GRAPH = 1

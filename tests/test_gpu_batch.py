@@ -24,7 +24,10 @@ def dev():
     return torch.device("cuda:0")
 
 
-def make_batch(seed, n, max_w=420, max_h=300, windows=(3, 5, 7, 9, 11, 13, 15)):
+ALL_WINDOWS = tuple(range(3, 32, 2))
+
+
+def make_batch(seed, n, max_w=420, max_h=300, windows=ALL_WINDOWS):
     rng = np.random.default_rng(seed)
     specs = []
     for j in range(n):
@@ -65,7 +68,10 @@ def test_uneven_batch_matches_oracle(dev, graph):
 def test_graph_replays_with_changing_batches(dev):
     with irfilter.Plan(32, 4000, graph=True) as plan:
         for rep in range(5):
-            specs = make_batch(100 + rep, 12 + 3 * rep, windows=(3, 5, 7, 9, 13))
+            # each batch uses another set of window classes (3..9, 11..15, single
+            # windows above 15x15), so most replays first capture a new graph
+            wins = [(3, 5, 7, 9), (3, 5, 7, 9, 13), (9, 17), (5, 25, 31), (3, 5, 7, 9)][rep]
+            specs = make_batch(100 + rep, 12 + 3 * rep, windows=wins)
             run_and_check(dev, plan, specs, f"replay {rep}")
             # unrelated eager work between replays
             x = torch.randn(1 << 20, device=dev)
@@ -139,6 +145,23 @@ def test_batch_validation(dev):
         with pytest.raises(irfilter.IrfError) as e:
             plan.run([(a, b, 4)])
         assert e.value.status == -5
+        with pytest.raises(irfilter.IrfError) as e:
+            plan.run([(a, b, 33)])
+        assert e.value.status == -5
         plan.run([(a, b, 3)])
         torch.cuda.synchronize()
         assert same(torch, b, a)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_every_window_class_in_one_batch(dev, graph):
+    # one frame per window 3..31 and pixel type, tiny and ragged sizes included
+    specs = []
+    for j, k in enumerate(ALL_WINDOWS):
+        for dt in ("u8", "u16"):
+            W, H = (37 + 29 * j) % 300 + 1, (11 + 17 * j) % 200 + 1
+            specs.append((synth.FrameSpec(W, H, dt, "mixed", 0.3, 0.0 if dt == "u8" else 20.0,
+                                          7000 + 2 * j + (dt == "u16")), k))
+    tiles = sum(irfilter.frame_tiles(s.width, s.height) for s, _ in specs)
+    with irfilter.Plan(len(specs), tiles, graph=graph) as plan:
+        run_and_check(dev, plan, specs, f"all classes graph={graph}")

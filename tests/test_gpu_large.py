@@ -172,10 +172,24 @@ def test_two_passes_and_stack(dev):
     assert int(cnt.item()) == tot
 
 
-def test_batch_rejects_large_windows(dev):
-    bufs = [to_dev(np.zeros((64, 64), dtype=np.uint16), dev) for _ in range(4)]
-    say("case large batch rejected")
-    with irfilter.Plan(2, 16) as plan:
+def test_batch_takes_large_windows_beside_small_ones(dev):
+    # batch plans run windows above 15x15 in kernels of their own, in the same
+    # batch as small windows; each frame equals its single launch, and 33 is refused
+    rng = np.random.default_rng(1717)
+    frames = [rng.integers(0, 1 << 14, size=(70 + 13 * i, 90 + 29 * i)).astype(np.uint16) for i in range(4)]
+    wins = [7, 17, 31, 9]
+    srcs = [to_dev(f, dev) for f in frames]
+    dsts = [torch.empty_like(s) for s in srcs]
+    refs = [torch.empty_like(s) for s in srcs]
+    say("case large windows in a batch")
+    tiles = sum(irfilter.frame_tiles(f.shape[1], f.shape[0]) for f in frames)
+    with irfilter.Plan(4, tiles) as plan:
+        plan.run([(s, d, k) for s, d, k in zip(srcs, dsts, wins)])
+        for s, r, k in zip(srcs, refs, wins):
+            irfilter.ir_filter_run(s, r, k)
+        torch.cuda.synchronize()
+        for d, r, k in zip(dsts, refs, wins):
+            assert torch.equal(d.view(torch.int16), r.view(torch.int16)), k
         with pytest.raises(irfilter.IrfError) as e:
-            plan.run([(bufs[0], bufs[1], 7), (bufs[2], bufs[3], 17)])
+            plan.run([(srcs[0], dsts[0], 7), (srcs[1], dsts[1], 33)])
         assert e.value.status == -5

@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1201_3972_amd import irfilter, serving
-from tests.gpu_helpers import say, to_host
+from paper_1201_3972_amd import irfilter, serving, synth
+from tests.gpu_helpers import say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -92,14 +92,43 @@ def test_request_larger_than_budget_is_reported(dev):
     srv.close()
 
 
-def test_windows_above_15_are_rejected_at_submission(dev):
-    # the server runs batch plans, which take windows up to IRF_MAX_BATCH_WINDOW
+def test_windows_above_31_are_rejected_at_submission(dev):
+    # the server runs batch plans, which take windows up to IRF_MAX_BATCH_WINDOW (31)
     src = torch.zeros((64, 64), dtype=torch.uint8).pin_memory()
     srv = serving.Server(memory_budget=1 << 24, max_inflight=2)
     try:
-        srv.submit(serving.Request(1, 0.0, src, 17))
+        srv.submit(serving.Request(1, 0.0, src, 33))
         with pytest.raises(irfilter.IrfError) as e:
             srv.run_until_idle()
         assert e.value.status == -5
     finally:
         srv.close()
+
+
+def test_large_windows_are_served_like_alone(dev):
+    # one-off frames with windows above 15x15 beside small-window ones: each
+    # result equals the same frame filtered alone, and the oracle
+    specs = [(synth.FrameSpec(300, 200, "u16", "mixed", 0.3, 20.0, 9100), 21),
+             (synth.FrameSpec(257, 129, "u8", "sp", 0.2, 0.0, 9101), 31),
+             (synth.FrameSpec(640, 512, "u16", "rv", 0.3, 20.0, 9102), 5),
+             (synth.FrameSpec(190, 77, "u8", "mixed", 0.4, 0.0, 9103), 17)]
+    srv = serving.Server(memory_budget=1 << 26, max_inflight=2)
+    reqs = []
+    try:
+        for i, (spec, k) in enumerate(specs):
+            f = synth.make_frame(spec)
+            t = torch.from_numpy(f.view(np.int16)).view(torch.uint16) if f.dtype == np.uint16 else torch.from_numpy(f)
+            reqs.append((f, k, serving.Request(i, 0.0005 * i, t.pin_memory(), k)))
+            srv.submit(reqs[-1][2])
+        say("case serving: large windows beside small ones")
+        srv.run_until_idle()
+    finally:
+        srv.close()
+    for f, k, r in reqs:
+        got = r.host_dst.view(torch.int16).numpy().view(np.uint16) if f.dtype == np.uint16 else r.host_dst.numpy()
+        src = to_dev(torch, f, dev)
+        alone = torch.empty_like(src)
+        irfilter.ir_filter_run(src, alone, k)
+        torch.cuda.synchronize()
+        assert np.array_equal(got, to_host(torch, alone)), (f.shape, k)
+        assert np.array_equal(got, oracle.fnr(f, k)[0]), (f.shape, k)

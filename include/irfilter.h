@@ -239,10 +239,13 @@ int ir_filter_plan_frame_tiles(const irf_plan *plan, int width, int height);
  * registered video stream use that stream's resident device slots, kept for
  * the server's lifetime; other frames take two blocks from a bounded device
  * arena, released when their result has reached the host), copies them host
- * -> device on one copy stream, filters them with ONE batched launch on a
- * compute stream, and copies the results back on a second copy stream, events
- * ordering the three (the two copy directions overlap).  Up to max_inflight steps are on the device at once, so
- * copies of one step overlap the kernels of another.  A request completes when
+ * -> device with ONE copy kernel on a copy stream (it reads the pinned host
+ * buffers through their device mappings; a buffer without one is copied with
+ * a copy command), filters them with ONE batched launch on a compute stream,
+ * and copies the results back with one copy kernel on a second copy stream,
+ * events ordering the three (the two copy directions overlap).  Up to
+ * max_inflight steps are on the device at once, so copies of one step overlap
+ * the kernels of another.  A request completes when
  * its device -> host copy has finished; its latency is completion time minus
  * its arrival time, both on the server's clock (seconds since creation).
  *

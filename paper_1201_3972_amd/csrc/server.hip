@@ -6,6 +6,8 @@
 
 #include <stdint.h>
 
+#include <string.h>
+
 #include <algorithm>
 #include <chrono>
 #include <deque>
@@ -38,6 +40,7 @@ struct Item {
     irf_request r;
     void *dsrc = nullptr, *ddst = nullptr;
     size_t dpitch = 0;
+    void *hsrc_dev = nullptr, *hdst_dev = nullptr;  // device views of the host buffers (null: none)
     Slot *slot = nullptr;
     size_t a_off = 0, b_off = 0, bytes = 0;  // arena blocks (one-off frames)
 };
@@ -45,10 +48,87 @@ struct Item {
 struct Step {
     std::vector<Item> items;
     hipEvent_t in = nullptr, kernel = nullptr, done = nullptr;
+    int table = -1;  // the piece tables (in, out) this step's copy kernels read
 };
 
 double seconds_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Frames move between pinned host memory and device memory by copy kernels, one
+// launch per step and direction: a piece is a band of rows of one frame (about
+// kPieceBytes), and each workgroup copies one piece.  The kernels read and
+// write the host buffers through their device mappings, so a step costs two
+// launches instead of one copy command per frame and direction.
+struct CopyPiece {
+    const uint8_t *src;
+    uint8_t *dst;
+    uint32_t spitch, dpitch;  // bytes between rows
+    uint32_t rowbytes, rows;
+};
+
+constexpr size_t kPieceBytes = 128 << 10;
+constexpr int kMaxPieces = 8192;  // per step and direction; further frames use copy commands
+constexpr int kCopyThreads = 256;
+
+__global__ __launch_bounds__(kCopyThreads) void copy_pieces_kernel(const CopyPiece *pieces) {
+    const CopyPiece p = pieces[blockIdx.x];
+    const bool vec = ((reinterpret_cast<uintptr_t>(p.src) | reinterpret_cast<uintptr_t>(p.dst) | p.spitch | p.dpitch |
+                       p.rowbytes) & 15u) == 0;
+    if (vec) {
+        // four 16-byte units per thread in flight, then their stores
+        const uint32_t upr = p.rowbytes >> 4, units = upr * p.rows;
+        for (uint32_t u0 = threadIdx.x; u0 < units; u0 += 4 * kCopyThreads) {
+            uint4 v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t u = u0 + (uint32_t)i * kCopyThreads;
+                if (u < units) {
+                    const uint32_t row = u / upr, col = u - row * upr;
+                    v[i] = *reinterpret_cast<const uint4 *>(p.src + (size_t)row * p.spitch + 16u * col);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t u = u0 + (uint32_t)i * kCopyThreads;
+                if (u < units) {
+                    const uint32_t row = u / upr, col = u - row * upr;
+                    *reinterpret_cast<uint4 *>(p.dst + (size_t)row * p.dpitch + 16u * col) = v[i];
+                }
+            }
+        }
+    } else {
+        const uint32_t units = p.rowbytes * p.rows;
+        for (uint32_t u = threadIdx.x; u < units; u += kCopyThreads) {
+            const uint32_t row = u / p.rowbytes, col = u - row * p.rowbytes;
+            p.dst[(size_t)row * p.dpitch + col] = p.src[(size_t)row * p.spitch + col];
+        }
+    }
+}
+
+// Split a frame copy into pieces (appended to `out` while it has room).
+bool add_pieces(std::vector<CopyPiece> &out, const void *src, size_t spitch, void *dst, size_t dpitch,
+                size_t rowbytes, int rows) {
+    const int band = (int)std::max<size_t>(1, kPieceBytes / std::max<size_t>(rowbytes, 1));
+    const int n = (rows + band - 1) / band;
+    if ((int)out.size() + n > kMaxPieces) return false;
+    for (int r0 = 0; r0 < rows; r0 += band) {
+        const int nr = std::min(band, rows - r0);
+        out.push_back({static_cast<const uint8_t *>(src) + (size_t)r0 * spitch,
+                       static_cast<uint8_t *>(dst) + (size_t)r0 * dpitch, (uint32_t)spitch, (uint32_t)dpitch,
+                       (uint32_t)rowbytes, (uint32_t)nr});
+    }
+    return true;
+}
+
+// The device address of a pinned host buffer, or null if it has none.
+void *device_view(const void *host) {
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, const_cast<void *>(host), 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return d;
 }
 
 }  // namespace
@@ -68,6 +148,12 @@ struct irf_server {
     std::vector<std::pair<uint64_t, double>> completed;
     size_t completed_head = 0;
     std::vector<irf_frame> frames;  // staging for one step
+    // piece tables in pinned host memory: 2 per in-flight step (in, out), and
+    // their device views; free table slots
+    CopyPiece *tables = nullptr;
+    CopyPiece *tables_dev = nullptr;
+    std::vector<int> free_tables;
+    std::vector<CopyPiece> pin, pout;  // pieces of the step being issued
     double last_arrival = 0.0;
     int steps = 0;
     std::chrono::steady_clock::time_point t0;
@@ -100,6 +186,7 @@ void free_server(irf_server *s) {
             if (sl.dst) (void)hipFree(sl.dst);
         }
     if (s->arena_mem) (void)hipFree(s->arena_mem);
+    if (s->tables) (void)hipHostFree(s->tables);
     if (s->h2d) (void)hipStreamDestroy(s->h2d);
     if (s->compute) (void)hipStreamDestroy(s->compute);
     if (s->d2h) (void)hipStreamDestroy(s->d2h);
@@ -128,6 +215,7 @@ void retire_step(irf_server *s, Step &st, double t) {
         }
     }
     for (hipEvent_t e : {st.in, st.kernel, st.done}) s->events.push_back(e);
+    if (st.table >= 0) s->free_tables.push_back(st.table);
 }
 
 int retire(irf_server *s, bool block) {
@@ -198,6 +286,8 @@ void admit(irf_server *s, std::vector<Item> &out) {
             it.ddst = s->arena_mem + it.b_off;
             it.dpitch = (size_t)r.width * bytes_of(r.dtype);
         }
+        it.hsrc_dev = device_view(r.host_src);
+        it.hdst_dev = device_view(r.host_dst);
         tiles += nt;
         out.push_back(it);
     }
@@ -215,6 +305,7 @@ void abandon_step(irf_server *s, Step &st, std::vector<Item> &items) {
     (void)hipGetLastError();
     for (hipEvent_t e : {st.in, st.kernel, st.done})
         if (e) s->events.push_back(e);
+    if (st.table >= 0) s->free_tables.push_back(st.table);
     for (auto it = items.rbegin(); it != items.rend(); ++it) {
         if (it->slot) {
             it->slot->busy = false;
@@ -227,15 +318,43 @@ void abandon_step(irf_server *s, Step &st, std::vector<Item> &items) {
     items.clear();
 }
 
+// The copies of one step in one direction: pieces for every frame whose host
+// buffer has a device view (one kernel launch), copy commands for the others.
+irf_status copy_step(irf_server *s, const std::vector<Item> &items, bool to_device, CopyPiece *table,
+                     const CopyPiece *table_dev, hipStream_t st) {
+    std::vector<CopyPiece> &pieces = to_device ? s->pin : s->pout;
+    pieces.clear();
+    for (const Item &it : items) {
+        const size_t row = (size_t)it.r.width * bytes_of(it.r.dtype);
+        const void *hsrc = to_device ? it.r.host_src : it.ddst;
+        void *hdst = to_device ? it.dsrc : it.r.host_dst;
+        void *hview = to_device ? it.hsrc_dev : it.hdst_dev;
+        const size_t spitch = to_device ? it.r.src_pitch : it.dpitch;
+        const size_t dpitch = to_device ? it.dpitch : it.r.dst_pitch;
+        const bool pieced = hview && spitch < ((size_t)1 << 32) && dpitch < ((size_t)1 << 32) &&
+                            add_pieces(pieces, to_device ? hview : hsrc, spitch, to_device ? hdst : hview, dpitch,
+                                       row, it.r.height);
+        if (!pieced && copy_frame(hdst, dpitch, hsrc, spitch, row, it.r.height,
+                                  to_device ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost, st) != hipSuccess)
+            return IRF_ERR_HIP;
+    }
+    if (!pieces.empty()) {
+        memcpy(table, pieces.data(), sizeof(CopyPiece) * pieces.size());
+        hipLaunchKernelGGL(copy_pieces_kernel, dim3((unsigned)pieces.size()), dim3(kCopyThreads), 0, st, table_dev);
+        if (hipGetLastError() != hipSuccess) return IRF_ERR_HIP;
+    }
+    return IRF_OK;
+}
+
 irf_status issue_step(irf_server *s, Step &st, const std::vector<Item> &items) {
     irf_status e;
     if ((e = take_event(s, &st.in)) || (e = take_event(s, &st.kernel)) || (e = take_event(s, &st.done))) return e;
-    for (const Item &it : items) {
-        const size_t row = (size_t)it.r.width * bytes_of(it.r.dtype);
-        if (copy_frame(it.dsrc, it.dpitch, it.r.host_src, it.r.src_pitch, row, it.r.height, hipMemcpyHostToDevice,
-                       s->h2d) != hipSuccess)
-            return IRF_ERR_HIP;
-    }
+    if (s->free_tables.empty()) return IRF_ERR_HIP;  // cannot happen: one table pair per in-flight step
+    st.table = s->free_tables.back();
+    s->free_tables.pop_back();
+    CopyPiece *tin = s->tables + (size_t)(2 * st.table) * kMaxPieces, *tout = tin + kMaxPieces;
+    const CopyPiece *din = s->tables_dev + (size_t)(2 * st.table) * kMaxPieces, *dout = din + kMaxPieces;
+    if ((e = copy_step(s, items, true, tin, din, s->h2d))) return e;
     if (hipEventRecord(st.in, s->h2d) != hipSuccess || hipStreamWaitEvent(s->compute, st.in, 0) != hipSuccess)
         return IRF_ERR_HIP;
     s->frames.clear();
@@ -247,12 +366,7 @@ irf_status issue_step(irf_server *s, Step &st, const std::vector<Item> &items) {
     if ((e = ir_filter_run_batch(plan, s->frames.data(), (int)s->frames.size(), nullptr, s->compute))) return e;
     if (hipEventRecord(st.kernel, s->compute) != hipSuccess || hipStreamWaitEvent(s->d2h, st.kernel, 0) != hipSuccess)
         return IRF_ERR_HIP;
-    for (const Item &it : items) {
-        const size_t row = (size_t)it.r.width * bytes_of(it.r.dtype);
-        if (copy_frame(it.r.host_dst, it.r.dst_pitch, it.ddst, it.dpitch, row, it.r.height, hipMemcpyDeviceToHost,
-                       s->d2h) != hipSuccess)
-            return IRF_ERR_HIP;
-    }
+    if ((e = copy_step(s, items, false, tout, dout, s->d2h))) return e;
     if (hipEventRecord(st.done, s->d2h) != hipSuccess) return IRF_ERR_HIP;
     return IRF_OK;
 }
@@ -302,6 +416,18 @@ irf_status ir_filter_server_create(irf_server **server, size_t arena_bytes, int 
             return IRF_ERR_NOMEM;
         }
         s->arena.reset(s->arena_bytes);
+        const size_t tbytes = sizeof(CopyPiece) * (size_t)kMaxPieces * 2 * (size_t)max_inflight;
+        if (hipHostMalloc(reinterpret_cast<void **>(&s->tables), tbytes, hipHostMallocCoherent) != hipSuccess ||
+            !(s->tables_dev = static_cast<CopyPiece *>(device_view(s->tables)))) {
+            if (s->tables) {
+                (void)hipHostFree(s->tables);
+                s->tables = nullptr;
+            }
+            free_server(s);
+            (void)hipGetLastError();
+            return IRF_ERR_NOMEM;
+        }
+        for (int i = max_inflight - 1; i >= 0; --i) s->free_tables.push_back(i);
         for (int i = 0; i < max_inflight; ++i) {
             irf_plan *p = nullptr;
             const irf_status st = ir_filter_plan_create(&p, max_batch_frames, max_batch_tiles, flags);

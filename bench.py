@@ -61,8 +61,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _counter_record(window: int):
-    """The counter record of one window's kernel, if it was taken on this source."""
+def _variant_key(window: int, threads: int, select: int) -> str:
+    return f"{window}/{threads}/{select}"
+
+
+def _counter_record(window: int, threads: int, select: int):
+    """The counter record of one stack kernel (window, workgroup size,
+    selection), if it was taken on this source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -70,29 +75,29 @@ def _counter_record(window: int):
         return None
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    return rec.get("windows", {}).get(str(window))
+    return rec.get("kernels", {}).get(_variant_key(window, threads, select))
 
 
-def load_traffic(window: int):
+def load_traffic(window: int, threads: int, select: int):
     """HBM bytes per launch measured by rocprofv3 counters, if taken on this source."""
-    ent = _counter_record(window)
+    ent = _counter_record(window, threads, select)
     return None if ent is None else float(ent["hbm_bytes_per_launch"])
 
 
-def load_valu(window: int):
+def load_valu(window: int, threads: int, select: int):
     """VALU instructions (wave-level) per launch from SQ_INSTS_VALU, if taken on this source."""
-    ent = _counter_record(window)
+    ent = _counter_record(window, threads, select)
     return None if ent is None or "valu_insts_per_launch" not in ent else float(ent["valu_insts_per_launch"])
 
 
-def _fnr_u16_window(name: str):
-    """The window of a 16-bit single-size FNR kernel's name, else None."""
+def _fnr_u16_variant(name: str):
+    """(window, threads, selection) of a 16-bit single-size FNR kernel's name, else None."""
     if "fnr_persistent_kernel<unsigned short," not in name:
         return None
     targs = [x.strip() for x in name.split("fnr_persistent_kernel<", 1)[1].split(">", 1)[0].split(",")]
-    if len(targs) < 3 or targs[2] != "1":  # MODE_FNR only
+    if len(targs) < 5 or targs[2] != "1":  # MODE_FNR only
         return None
-    return int(targs[1])
+    return int(targs[1]), int(targs[3]), int(targs[4])
 
 
 def ingest_counters(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out_path=TRAFFIC_FILE) -> dict:
@@ -124,15 +129,15 @@ def ingest_counters(fetch_csv, write_csv, cfetch_csv, cwrite_csv, out_path=TRAFF
     write = per_kernel(write_csv, "WRITE_SIZE")
     rec = {"source_hash": kernel_source_hash(), "copy_calibration": {
         "bytes": 1 << 30, "fetch_kib": fk, "write_kib": wk, "fetch_scale": ff, "write_scale": wf},
-        "windows": {}}
+        "kernels": {}}
     for name, vs in fetch.items():
-        k = _fnr_u16_window(name)
-        if k is None:
+        var = _fnr_u16_variant(name)
+        if var is None or name not in write:
             continue
         f_kib = sum(vs) / len(vs)
         w_kib = sum(write[name]) / len(write[name])
-        rec["windows"][str(k)] = {"kernel": name, "fetch_kib": f_kib, "write_kib": w_kib,
-                                  "hbm_bytes_per_launch": f_kib * 1024 * ff + w_kib * 1024 * wf}
+        rec["kernels"][_variant_key(*var)] = {"kernel": name, "fetch_kib": f_kib, "write_kib": w_kib,
+                                              "hbm_bytes_per_launch": f_kib * 1024 * ff + w_kib * 1024 * wf}
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
@@ -150,12 +155,12 @@ def ingest_sq(sq_csv, out_path=TRAFFIC_FILE) -> dict:
     vals = {}
     with open(sq_csv) as fh:
         for r in csv.DictReader(fh):
-            k = _fnr_u16_window(r["Kernel_Name"])
-            if k is not None and r["Counter_Name"] == "SQ_INSTS_VALU":
-                vals.setdefault(k, []).append(float(r["Counter_Value"]))
-    for k, vs in vals.items():
-        if str(k) in rec["windows"]:
-            rec["windows"][str(k)]["valu_insts_per_launch"] = sum(vs) / len(vs)
+            var = _fnr_u16_variant(r["Kernel_Name"])
+            if var is not None and r["Counter_Name"] == "SQ_INSTS_VALU":
+                vals.setdefault(_variant_key(*var), []).append(float(r["Counter_Value"]))
+    for key, vs in vals.items():
+        if key in rec["kernels"]:
+            rec["kernels"][key]["valu_insts_per_launch"] = sum(vs) / len(vs)
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
@@ -543,9 +548,10 @@ def section_f1(torch, irfilter, synth, oracle, dev, rounds: int = 5, reps: int =
 
 
 def section_f2(torch, irfilter, synth, oracle, dev, frames: int = 8, reps: int = 3) -> dict:
-    """Windows above 15x15 (17x17 .. 31x31, lane-group bisection) on a stack of
-    1920x1080 u16 frames with 40 % mixed impulses, 15x15 (networks) beside them:
-    ms per frame.  Parity: a whole 480x270 frame of the same recipe against the
+    """Windows above 15x15 (17x17 .. 31x31) on a stack of 1920x1080 u16 frames
+    with 40 % mixed impulses, 15x15 (networks) beside them: ms per frame for
+    each selection of the large windows (lane-group bisection and the
+    histogram radix select), 256-thread workgroups.  Parity: a whole 480x270 frame of the same recipe against the
     oracle, and 512 sampled pixels of the timed stack against the oracle's
     pointwise evaluation."""
     windows = (15, 17, 19, 21, 23, 25, 27, 29, 31)
@@ -568,28 +574,38 @@ def section_f2(torch, irfilter, synth, oracle, dev, frames: int = 8, reps: int =
                      f"sampled pixels (corners included) of each of the {frames} timed frames equal the oracle's "
                      "pointwise result", "windows": {}}
     for k in windows:
-        irfilter.ir_filter_run(s_src, s_dst, k, flagged_count=cnt)
-        torch.cuda.synchronize()
-        want, wc = oracle.fnr(small, k)
-        if not np.array_equal(s_dst.view(torch.int16).cpu().numpy().view(np.uint16), want) or \
-                int(cnt.item()) != int(wc[0]):
-            raise RuntimeError(f"f2 {k}x{k}: 480x270 frame differs from the oracle")
-        irfilter.ir_filter_run_frames(src, dst, k, flagged_count=cnt)
-        torch.cuda.synchronize()
-        flagged = int(cnt.item())
-        wpts = oracle.fnr_at(f, k, pts)
-        for i in range(frames):
-            got = dst[i].view(torch.int16).cpu().numpy().view(np.uint16)
-            if not np.array_equal(np.array([got[y, x] for x, y in pts], dtype=np.uint32), wpts):
-                raise RuntimeError(f"f2 {k}x{k}: sampled pixels of frame {i} differ from the oracle")
-        best = float("inf")
-        for _ in range(reps):
-            best = min(best, _timed(torch, lambda: irfilter.ir_filter_run_frames(src, dst, k), 2))
-        th, sel = irfilter.get_tuning("u16", k)
-        out["windows"][str(k)] = {"ms_per_frame": round(best / frames, 4),
-                                  "mpx_per_s": round(frames * W * H / best / 1e3, 1),
-                                  "flagged_fraction": round(flagged / (frames * W * H), 4),
-                                  "threads": th, "select": irfilter.SELECT_NAMES[sel]}
+        sels = ([irfilter.IRF_SELECT_NETWORK] if k <= 15 else
+                [irfilter.IRF_SELECT_GROUP, irfilter.IRF_SELECT_HIST])
+        before = irfilter.get_tuning("u16", k)
+        ent = {}
+        try:
+            for sel in sels:
+                irfilter.set_tuning("u16", k, 256, sel)
+                irfilter.ir_filter_run(s_src, s_dst, k, flagged_count=cnt)
+                torch.cuda.synchronize()
+                want, wc = oracle.fnr(small, k)
+                if not np.array_equal(s_dst.view(torch.int16).cpu().numpy().view(np.uint16), want) or \
+                        int(cnt.item()) != int(wc[0]):
+                    raise RuntimeError(f"f2 {k}x{k}: 480x270 frame differs from the oracle")
+                irfilter.ir_filter_run_frames(src, dst, k, flagged_count=cnt)
+                torch.cuda.synchronize()
+                flagged = int(cnt.item())
+                wpts = oracle.fnr_at(f, k, pts)
+                for i in range(frames):
+                    got = dst[i].view(torch.int16).cpu().numpy().view(np.uint16)
+                    if not np.array_equal(np.array([got[y, x] for x, y in pts], dtype=np.uint32), wpts):
+                        raise RuntimeError(f"f2 {k}x{k}: sampled pixels of frame {i} differ from the oracle")
+                best = float("inf")
+                for _ in range(reps):
+                    best = min(best, _timed(torch, lambda: irfilter.ir_filter_run_frames(src, dst, k), 2))
+                ent[irfilter.SELECT_NAMES[sel]] = {"ms_per_frame": round(best / frames, 4),
+                                                   "mpx_per_s": round(frames * W * H / best / 1e3, 1),
+                                                   "flagged_fraction": round(flagged / (frames * W * H), 4)}
+        finally:
+            irfilter.set_tuning("u16", k, *before)
+        out["windows"][str(k)] = {"threads": 256, **ent}
+        if len(ent) > 1:
+            out["windows"][str(k)]["faster"] = min(ent, key=lambda n: ent[n]["ms_per_frame"])
         log(f"f2 {k}x{k}: {out['windows'][str(k)]}")
     return out
 
@@ -838,10 +854,10 @@ def main() -> int:
     dom = max(windows, key=lambda k: kern_ms[k])
     bytes_per_launch = BYTES_PER_PX * N * W * H
     achieved = bytes_per_launch / (kern_ms[dom] * 1e-3) / 1e9
-    traffic = load_traffic(dom)
+    traffic = load_traffic(dom, *chosen[dom])
     # the vector ALU view of the same launch: the kernel is bound by its
     # integer work before the HBM roofline (wave instructions x 64 lanes)
-    valu_insts = load_valu(dom)
+    valu_insts = load_valu(dom, *chosen[dom])
     valu = None
     if valu_insts is not None:
         lane_t = valu_insts * 64 / (kern_ms[dom] * 1e-3) / 1e12

@@ -327,15 +327,17 @@ void ir_filter_server_destroy(irf_server *server);
  *   IRF_SELECT_NETWORK  forgetful selection networks, two windows per lane
  *                       (windows up to 15x15)
  *   IRF_SELECT_BISECT   grey-level bisection, one window per lane (up to 15x15)
- *   IRF_SELECT_GROUP    grey-level bisection, one window per group of 8 or 16
- *                       lanes (the only choice above 15x15)
- * Untuned defaults: 256 threads for 7x7 and above 15x15, else 128; networks
+ *   IRF_SELECT_GROUP    grey-level bisection, one window per group of 4, 8 or
+ *                       16 lanes (above 15x15)
+ *   IRF_SELECT_HIST     two-pass radix select over a 256-bin LDS histogram,
+ *                       one window per group of 16 lanes (above 15x15)
+ * Untuned defaults: 256 threads for 5x5, 7x7 and above 15x15, else 128; networks
  * up to 15x15, group bisection above.
  * ir_filter_set_tuning(dtype, window, 0, 0)
  * restores the default; an unavailable combination returns IRF_ERR_TUNING.
  * The autotuner of the Python package measures the choices and sets them.
  */
-typedef enum { IRF_SELECT_NETWORK = 1, IRF_SELECT_BISECT = 2, IRF_SELECT_GROUP = 3 } irf_select;
+typedef enum { IRF_SELECT_NETWORK = 1, IRF_SELECT_BISECT = 2, IRF_SELECT_GROUP = 3, IRF_SELECT_HIST = 4 } irf_select;
 
 irf_status ir_filter_get_tuning(irf_dtype dtype, int window, int *threads, int *select);
 irf_status ir_filter_set_tuning(irf_dtype dtype, int window, int threads, int select);

@@ -41,11 +41,12 @@ FUSION_MARGIN = 1.03  # a fixed fusion choice replaces the automatic one only if
 
 def candidates(window: int) -> List[Tuple[int, int]]:
     """Every (threads, select) with a kernel for this window: networks and
-    one-lane bisection up to 15x15, group bisection above."""
+    one-lane bisection up to 15x15, group bisection and the histogram radix
+    select above."""
     if window <= NETWORK_MAX_WINDOW:
         sels = [irfilter.IRF_SELECT_NETWORK, irfilter.IRF_SELECT_BISECT]
     else:
-        sels = [irfilter.IRF_SELECT_GROUP]
+        sels = [irfilter.IRF_SELECT_GROUP, irfilter.IRF_SELECT_HIST]
     return [(t, s) for t in (128, 256) for s in sels]
 
 

@@ -46,19 +46,22 @@ constexpr int kTileW = 128;                  // output columns per tile
 constexpr int kThreadsX = kTileW / 4;        // 32 threads across, 4 columns each
 constexpr int kStrips = kThreads / kThreadsX;  // 4 strips of R rows
 // Selection algorithm: forgetful selection networks on two windows per lane,
-// grey-level bisection on one window per lane, or grey-level bisection on one
-// window per group of 8 or 16 lanes (the windows above 15x15, whose values no
-// longer fit one lane's registers).
-enum Select : int { kSelectNetwork = 1, kSelectBisect = 2, kSelectGroup = 3 };
+// grey-level bisection on one window per lane, grey-level bisection on one
+// window per group of 8 or 16 lanes, or a two-pass radix select over LDS
+// histograms on one window per group of 16 lanes (the last two for windows
+// above 15x15, whose values no longer fit one lane's registers).
+enum Select : int { kSelectNetwork = 1, kSelectBisect = 2, kSelectGroup = 3, kSelectHist = 4 };
 constexpr int kNetworkMaxWindow = 15;
-// Untuned choices of the stack kernels: 7x7 takes 256-thread workgroups on tiles
-// of twice the height, which fill its selection waves better (a 128x32 tile
-// holds about 80 window pairs at the usual impulse rates, just over one wave's
-// worth); the other windows up to 15x15 run faster with the smaller tile, those
-// above (group bisection) with the larger one.  Networks beat
-// bisection at every window (by 2.4x at 15x15).  The host's tuning table starts
-// from these and an autotuner may replace them.
-constexpr int default_threads(int K) { return (K == 7 || K > kNetworkMaxWindow) ? 256 : 128; }
+constexpr int kHistLanes = 16;  // lanes per window of the histogram radix select
+constexpr int kHistBins = 256;  // bins of one radix pass
+// Untuned choices of the stack kernels: 5x5 and 7x7 take 256-thread workgroups
+// on tiles of twice the height, which fill their selection waves better (a
+// 128x32 tile holds about 80 window pairs at 7x7 at the usual impulse rates,
+// just over one wave's worth); the other windows up to 15x15 run faster with
+// the smaller tile, those above (group bisection) with the larger one.
+// Networks beat bisection at every window (by 2.4x at 15x15).  The host's
+// tuning table starts from these and an autotuner may replace them.
+constexpr int default_threads(int K) { return (K == 5 || K == 7 || K > kNetworkMaxWindow) ? 256 : 128; }
 constexpr int default_select(int K) { return K <= kNetworkMaxWindow ? kSelectNetwork : kSelectGroup; }
 constexpr int kMaxWindow = 31;
 
@@ -977,6 +980,125 @@ __device__ __forceinline__ uint32_t median_group(const uint16_t *w, int g, uint3
     return lo;
 }
 
+// Inclusive prefix sum inside each row of 16 lanes (DPP row shifts; lanes
+// shifted in from outside the row read 0).
+__device__ __forceinline__ uint32_t row_inclusive_sum(uint32_t v) {
+    constexpr int kRowShr = 0x110;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 2, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 4, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 8, 0xf, 0xf, true);
+    return (uint32_t)x;
+}
+
+// One 256-bin histogram pass of the radix select: the group's 16 lanes read
+// their 16 bins each, find the bin holding element `rank` (0-based) of the
+// counted values, clear their bins, and return ((bin + 1) << 16 | rank within
+// the bin) in every lane of the group.
+__device__ __forceinline__ uint32_t hist_find(uint32_t *bins, int g, uint32_t rank) {
+    const uint4 *b4 = reinterpret_cast<const uint4 *>(bins + 16 * g);
+    uint32_t c[16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint4 x = b4[q];
+        c[4 * q] = x.x;
+        c[4 * q + 1] = x.y;
+        c[4 * q + 2] = x.z;
+        c[4 * q + 3] = x.w;
+    }
+    uint32_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) tot += c[j];
+    uint32_t cum = row_inclusive_sum(tot) - tot;  // values in the bins of lower lanes
+    uint32_t key = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t next = cum + c[j];
+        if (cum <= rank && rank < next) key = ((uint32_t)(16 * g + j + 1) << 16) | (rank - cum);
+        cum = next;
+    }
+    uint4 *w4 = reinterpret_cast<uint4 *>(bins + 16 * g);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w4[q] = make_uint4(0u, 0u, 0u, 0u);
+    return group_reduce<kHistLanes>(key, [](uint32_t a, uint32_t b) { return max(a, b); });
+}
+
+// Median of the window whose top-left value is w, computed by the group member
+// g (0..15) with its group's LDS histogram `bins` (all zero on entry and on
+// return); every member returns it.  A two-pass radix select on the offsets
+// from the window minimum: pass 1 counts the values by their top 8 bits below
+// the range's bit length and finds the bin holding the median, pass 2 counts
+// the values of that bin by their remaining low bits (at most 8, for 16-bit
+// data) and finds the median itself.  Lane g holds values g, g + 16, g + 32,
+// ... of S_xy, two per register; the slots past the window's end repeat the
+// lane's first value and are never counted.
+template <int K>
+__device__ __forceinline__ uint32_t median_hist(const uint16_t *w, int g, uint32_t *bins) {
+    constexpr int N = K * K, L = kHistLanes, V = (N + L - 1) / L, V2 = (V + 1) / 2;
+    constexpr int pitch = Geometry<K>::pitch;
+    constexpr uint32_t rank = (N - 1) / 2;
+    static_assert(K > L, "a lane's next value is at most one window row further");
+    // value m of the lane exists when 16 m + g < N: only the last two can be missing
+    auto valid = [&](int m) { return m < V - 2 || (m < V && 16 * m + g < N); };
+    const uint16_t first = w[g];
+    int off = g, col = g;
+    auto next = [&](int m) -> uint16_t {
+        const uint16_t x = valid(m) ? w[off] : first;
+        col += L;
+        off += L;
+        if (col >= K) {
+            col -= K;
+            off += pitch - K;
+        }
+        return x;
+    };
+    uint32_t v[V2];
+#pragma unroll
+    for (int j = 0; j < V2; ++j) {
+        u16x2 p;  // built element-wise so that each value loads straight into its half
+        p.x = next(2 * j);
+        p.y = next(2 * j + 1);
+        v[j] = __builtin_bit_cast(uint32_t, p);
+    }
+    uint32_t pmn = v[0], pmx = v[0];
+#pragma unroll
+    for (int j = 1; j < V2; ++j) {
+        pmn = pk_min(pmn, v[j]);
+        pmx = pk_max(pmx, v[j]);
+    }
+    uint32_t mn = min(pmn & 0xffffu, pmn >> 16), mx = max(pmx & 0xffffu, pmx >> 16);
+    mn = group_reduce<L>(mn, [](uint32_t a, uint32_t b) { return min(a, b); });
+    mx = group_reduce<L>(mx, [](uint32_t a, uint32_t b) { return max(a, b); });
+    const uint32_t range = mx - mn;
+    const int bits = range == 0 ? 0 : 32 - __builtin_clz(range);
+    const uint32_t s1 = bits > 8 ? (uint32_t)bits - 8u : 0u;
+    const uint32_t mnp = mn | (mn << 16);
+    // offsets from the minimum, two per register (no half can borrow: every
+    // value is at least the minimum)
+#pragma unroll
+    for (int j = 0; j < V2; ++j) v[j] = v[j] - mnp;
+    // pass 1: the top 8 bits of each offset's range
+#pragma unroll
+    for (int j = 0; j < V2; ++j) {
+        if (valid(2 * j)) atomicAdd(bins + __builtin_amdgcn_ubfe(v[j], s1, 8), 1u);
+        if (valid(2 * j + 1)) atomicAdd(bins + __builtin_amdgcn_ubfe(v[j], 16 + s1, 8), 1u);
+    }
+    const uint32_t k1 = hist_find(bins, g, rank);
+    const uint32_t b1 = (k1 >> 16) - 1, r1 = k1 & 0xffffu;
+    if (s1 == 0) return mn + b1;
+    // pass 2: the low s1 bits of the offsets in bin b1
+#pragma unroll
+    for (int j = 0; j < V2; ++j) {
+        if (valid(2 * j) && __builtin_amdgcn_ubfe(v[j], s1, 8) == b1)
+            atomicAdd(bins + __builtin_amdgcn_ubfe(v[j], 0, s1), 1u);
+        if (valid(2 * j + 1) && __builtin_amdgcn_ubfe(v[j], 16 + s1, 8) == b1)
+            atomicAdd(bins + __builtin_amdgcn_ubfe(v[j], 16, s1), 1u);
+    }
+    const uint32_t k2 = hist_find(bins, g, r1);
+    return mn + (b1 << s1) + ((k2 >> 16) - 1);
+}
+
 // ---------------------------------------------------------------------------
 // wave / workgroup prefix sums
 // ---------------------------------------------------------------------------
@@ -1087,13 +1209,26 @@ __device__ __forceinline__ TileRange xcd_range(int b, int G, int total) {
     return {tb + local, te, nx};
 }
 
-template <int K, int NT = kThreads>
+// Radix-select histograms (kSelectHist): 256 bins per group of kHistLanes lanes.
+template <int NT, bool ON>
+struct HistSpace {};
+template <int NT>
+struct HistSpace<NT, true> {
+    alignas(16) uint32_t bins[NT / kHistLanes][kHistBins];
+};
+
+template <int K, int NT = kThreads, int SEL = 0>
 struct TileSmem {
     using G = Geometry<K, NT>;
     uint16_t tile[G::rows * G::pitch];
     uint16_t list[G::tile_px];  // LDS offsets of flagged centres, then their medians
     uint32_t count;             // list length
+    HistSpace<NT, SEL == kSelectHist> hist;
 };
+
+// The shared memory of a kernel with selection SEL (histograms only for kSelectHist).
+template <int K, int NT, int SEL>
+using SmemFor = TileSmem<K, NT, SEL == kSelectHist ? kSelectHist : 0>;
 
 // 3 x 3 windows take a dense path instead of steps 3 and 4: at the flag rates
 // of 3 x 3 (a quarter to half of the pixels) computing every pixel's median in
@@ -1167,10 +1302,11 @@ __device__ __forceinline__ void dense3_block(const uint16_t *tile, int strip, in
 // pixels of the calling wave (wave-uniform).  PRIO: the wave runs from here on
 // at the highest priority and the caller lowers it again (see process_tile).
 template <int K, int NT, int SEL, bool PRIO = false>
-__device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32_t flags, int centre0,
+__device__ __forceinline__ uint32_t median_into_tile(SmemFor<K, NT, SEL> &sm, uint32_t flags, int centre0,
                                                      int rot, uint32_t pk_one) {
     using G = Geometry<K, NT>;
-    static_assert(SEL == kSelectGroup || (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
+    static_assert(((SEL == kSelectGroup || SEL == kSelectHist) && K > kNetworkMaxWindow) ||
+                      (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
                   "no kernel of this selection for this window");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -1198,7 +1334,17 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
     //    rotates with `rot` (waves sit on fixed SIMDs)
     constexpr int corner = G::r * G::pitch + G::r;
     const uint32_t slot = ((uint32_t)tid + 64u * (uint32_t)rot) % NT;
-    if constexpr (SEL == kSelectGroup) {
+    if constexpr (SEL == kSelectHist) {
+        // one window per group of 16 lanes, each group with its own histogram
+        constexpr int L = kHistLanes, NG = NT / L;
+        const int g = tid % L, grp = tid / L;
+        const uint32_t gslot = ((uint32_t)grp + (64u / L) * (uint32_t)rot) % NG;
+        for (uint32_t i = gslot; i < total; i += NG) {
+            const uint32_t e0 = sm.list[i];
+            const uint32_t med = median_hist<K>(sm.tile + e0 - corner, g, sm.hist.bins[grp]);
+            if (g == 0) sm.list[i] = (uint16_t)med;
+        }
+    } else if constexpr (SEL == kSelectGroup) {
         // one window per group of lanes: all lanes of a group read the entry
         // before its first lane overwrites it (a group lies inside one wave)
         constexpr int L = GroupPlan<K>::lanes, NG = NT / L;
@@ -1250,9 +1396,10 @@ __device__ __forceinline__ uint32_t median_into_tile(TileSmem<K, NT> &sm, uint32
 // the highest priority (load_tile, EARLY), this measured 9-12% faster at 5x5
 // to 9x9.
 template <typename T, int K, int MODE, int NT = kThreads, int SEL = default_select(K), bool PRIO = false>
-__device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, TileSmem<K, NT> &sm) {
+__device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, SmemFor<K, NT, SEL> &sm) {
     using G = Geometry<K, NT>;
-    static_assert(SEL == kSelectGroup || (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
+    static_assert(((SEL == kSelectGroup || SEL == kSelectHist) && K > kNetworkMaxWindow) ||
+                      (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
                   "no kernel of this selection for this window");
     constexpr int R = G::R;
     const int f = tile / a.tiles_per_frame;
@@ -1359,10 +1506,14 @@ __device__ __forceinline__ void tile_origin(const StackArgs &a, int tile, int th
 template <typename T, int K, int MODE, int NT, int SEL>
 __global__ __launch_bounds__(NT) void fnr_persistent_kernel(StackArgs a) {
     using G = Geometry<K, NT>;
-    __shared__ __attribute__((aligned(16))) TileSmem<K, NT> sm;
+    __shared__ __attribute__((aligned(16))) SmemFor<K, NT, SEL> sm;
     const TileRange rg = xcd_range(blockIdx.x, gridDim.x, a.total_tiles);
     const bool aligned = a.aligned != 0;
     uint32_t flagged = 0;  // this wave's noisy pixels over all its tiles
+    if constexpr (SEL == kSelectHist) {
+        // histograms start empty (the first tile's load barrier orders this)
+        for (int i = threadIdx.x; i < NT / kHistLanes * kHistBins; i += NT) (&sm.hist.bins[0][0])[i] = 0u;
+    }
     for (int t = rg.first; t < rg.end; t += rg.stride) {
         int f, x0, y0;
         tile_origin(a, t, G::TH, f, x0, y0);

@@ -22,11 +22,12 @@ struct Tuning {
 inline Tuning default_tuning(int window) { return {default_threads(window), default_select(window)}; }
 
 // Whether a kernel exists for (window, tuning): 128 or 256 threads; networks
-// and one-lane bisection up to 15x15, group bisection above.
+// and one-lane bisection up to 15x15, group bisection and the histogram radix
+// select above.
 inline bool tuning_available(int window, Tuning t) {
     if (t.threads != 128 && t.threads != 256) return false;
     if (window <= kNetworkMaxWindow) return t.select == kSelectNetwork || t.select == kSelectBisect;
-    return t.select == kSelectGroup;
+    return t.select == kSelectGroup || t.select == kSelectHist;
 }
 
 // Launch the stack kernel of the pixel type for a.total_tiles tiles; false if
@@ -111,6 +112,10 @@ bool launch_threads(int select, const StackArgs &a, hipStream_t s) {
         launch_variant<T, K, MODE, NT, default_select(K)>(a, s);
         return true;
     } else if constexpr (K > kNetworkMaxWindow) {
+        if (select == kSelectHist) {
+            launch_variant<T, K, MODE, NT, kSelectHist>(a, s);
+            return true;
+        }
         if (select != kSelectGroup) return false;
         launch_variant<T, K, MODE, NT, kSelectGroup>(a, s);
         return true;

@@ -13,27 +13,28 @@ K7 = "void irf::fnr_persistent_kernel<unsigned short, 7, 1, 256, 1>(irf::StackAr
 K5 = "void irf::fnr_persistent_kernel<unsigned short, 5, 1, 128, 1>(irf::StackArgs)"
 
 
-def test_kernel_names_map_to_windows():
-    assert bench._fnr_u16_window(K7) == 7
-    assert bench._fnr_u16_window(K5) == 5
+def test_kernel_names_map_to_variants():
+    assert bench._fnr_u16_variant(K7) == (7, 256, 1)
+    assert bench._fnr_u16_variant(K5) == (5, 128, 1)
     # detection-only mode, 8-bit kernels and other kernels carry no record
-    assert bench._fnr_u16_window(K7.replace("7, 1, 256", "7, 0, 256")) is None
-    assert bench._fnr_u16_window(K7.replace("unsigned short", "unsigned char")) is None
-    assert bench._fnr_u16_window("__amd_rocclr_copyBuffer") is None
+    assert bench._fnr_u16_variant(K7.replace("7, 1, 256", "7, 0, 256")) is None
+    assert bench._fnr_u16_variant(K7.replace("unsigned short", "unsigned char")) is None
+    assert bench._fnr_u16_variant("__amd_rocclr_copyBuffer") is None
 
 
 def test_committed_record_is_read_only_on_its_own_sources():
     with open(bench.TRAFFIC_FILE) as fh:
         rec = json.load(fh)
-    for k in ("5", "7"):
-        ent = rec["windows"][k]
+    assert rec["kernels"], "the record holds at least one kernel"
+    for key, ent in rec["kernels"].items():
         assert ent["hbm_bytes_per_launch"] > bench.BYTES_PER_PX * 1024 * 640 * 512
         assert ent["valu_insts_per_launch"] > 0
-    if rec["source_hash"] == bench.kernel_source_hash():
-        assert bench.load_traffic(7) == rec["windows"]["7"]["hbm_bytes_per_launch"]
-        assert bench.load_valu(7) == rec["windows"]["7"]["valu_insts_per_launch"]
-    else:  # the kernels changed since the counters were taken: reported as null
-        assert bench.load_traffic(7) is None and bench.load_valu(7) is None
+        var = tuple(int(x) for x in key.split("/"))
+        if rec["source_hash"] == bench.kernel_source_hash():
+            assert bench.load_traffic(*var) == ent["hbm_bytes_per_launch"]
+            assert bench.load_valu(*var) == ent["valu_insts_per_launch"]
+        else:  # the kernels changed since the counters were taken: reported as null
+            assert bench.load_traffic(*var) is None and bench.load_valu(*var) is None
 
 
 def _write_csv(path, rows):
@@ -59,12 +60,12 @@ def test_ingest_round_trip(tmp_path):
     cc = rec["copy_calibration"]
     assert cc["fetch_scale"] == pytest.approx(2.0) and cc["write_scale"] == pytest.approx(1.0)
     # fetch averaged over dispatches and doubled, writes taken as they are
-    assert rec["windows"]["7"]["hbm_bytes_per_launch"] == pytest.approx(2000 * 1024 * 2 + 500 * 1024)
+    assert rec["kernels"]["7/256/1"]["hbm_bytes_per_launch"] == pytest.approx(2000 * 1024 * 2 + 500 * 1024)
     _write_csv(tmp_path / "sq.csv", [(K7, "SQ_INSTS_VALU", 100.0), (K7, "SQ_INSTS_VALU", 300.0),
                                      (K7, "SQ_WAVES", 7.0), (K5, "SQ_INSTS_VALU", 50.0)])
     rec = bench.ingest_sq(str(tmp_path / "sq.csv"), out_path=out)
-    assert rec["windows"]["7"]["valu_insts_per_launch"] == 200.0
-    assert rec["windows"]["5"]["valu_insts_per_launch"] == 50.0
+    assert rec["kernels"]["7/256/1"]["valu_insts_per_launch"] == 200.0
+    assert rec["kernels"]["5/128/1"]["valu_insts_per_launch"] == 50.0
     # a record taken on other sources is refused
     with open(out) as fh:
         stale = json.load(fh)

@@ -36,11 +36,12 @@ def dev():
 
 @pytest.fixture
 def threads():
-    """Set the workgroup size of (dtype, window) for one test; restores the defaults after."""
+    """Set the workgroup size (and selection) of (dtype, window) for one test;
+    restores the defaults after."""
     touched = []
 
-    def set_(dt, k, t):
-        irfilter.set_tuning(dt, k, t, irfilter.IRF_SELECT_GROUP)
+    def set_(dt, k, t, sel=irfilter.IRF_SELECT_GROUP):
+        irfilter.set_tuning(dt, k, t, sel)
         touched.append((dt, k))
 
     yield set_
@@ -82,14 +83,18 @@ def check_fnr(frame, k, dev, passes=1, tag=""):
     np.testing.assert_array_equal(cnt.cpu().numpy().astype(np.uint64), wcounts)
 
 
+SELECTS = [irfilter.IRF_SELECT_GROUP, irfilter.IRF_SELECT_HIST]
+
+
+@pytest.mark.parametrize("sel", SELECTS)
 @pytest.mark.parametrize("t", [128, 256])
 @pytest.mark.parametrize("k", LARGE)
 @pytest.mark.parametrize("dt", ["u8", "u16"])
-def test_fnr_every_window(dev, threads, dt, k, t):
+def test_fnr_every_window(dev, threads, dt, k, t, sel):
     # 2 tiles across (the second ragged) and several tile rows, mixed impulses
-    threads(dt, k, t)
+    threads(dt, k, t, sel)
     f = synth.make_frame(synth.FrameSpec(203, 149, dt, "mixed", 0.3, 0.0 if dt == "u8" else 20.0, 1700 + k))
-    check_fnr(f, k, dev, tag=f"t{t}")
+    check_fnr(f, k, dev, tag=f"t{t} {irfilter.SELECT_NAMES[sel]}")
 
 
 @pytest.mark.parametrize("k", [17, 23, 31])
@@ -125,9 +130,11 @@ def test_shapes(dev, W, H, k):
         check_fnr(f, k, dev)
 
 
+@pytest.mark.parametrize("sel", SELECTS)
 @pytest.mark.parametrize("k", [17, 31])
 @pytest.mark.parametrize("dt", ["u8", "u16"])
-def test_ties_and_extremes(dev, dt, k):
+def test_ties_and_extremes(dev, threads, dt, k, sel):
+    threads(dt, k, 256, sel)
     rng = np.random.default_rng(k + (dt == "u16"))
     check_fnr(synth.random_frame(rng, 140, 90, dt, alphabet=3), k, dev, tag="ties")
     vmax = 255 if dt == "u8" else 65535
@@ -145,11 +152,34 @@ def test_ties_and_extremes(dev, dt, k):
         assert int(cnt.item()) == f.size
 
 
-def test_full_16bit_range(dev):
+@pytest.mark.parametrize("sel", SELECTS)
+def test_full_16bit_range(dev, threads, sel):
     rng = np.random.default_rng(31)
     f = rng.integers(0, 65536, size=(80, 150)).astype(np.uint16)
     for k in (17, 21, 31):
-        check_fnr(f, k, dev, tag="16-bit")
+        threads("u16", k, 256, sel)
+        check_fnr(f, k, dev, tag=f"16-bit {irfilter.SELECT_NAMES[sel]}")
+
+
+@pytest.mark.parametrize("k", [17, 25, 31])
+def test_hist_masked_and_plain_median(dev, threads, k):
+    # the radix select serves every mode that selects: masked and plain medians
+    for dt in ("u8", "u16"):
+        threads(dt, k, 128, irfilter.IRF_SELECT_HIST)
+        f = synth.make_frame(synth.FrameSpec(141, 75, dt, "mixed", 0.3, 0.0 if dt == "u8" else 20.0, 1850 + k))
+        src = to_dev(f, dev)
+        mask = torch.zeros(f.shape, dtype=torch.uint8, device=dev)
+        irfilter.ir_filter_detect(src, mask, k)
+        dst = torch.empty_like(src)
+        say(f"case hist masked median {dt} k={k}")
+        irfilter.ir_filter_median(src, dst, k, mask=mask)
+        torch.cuda.synchronize()
+        wmask, _ = oracle.detect(f, k)
+        assert_same(to_host(dst), oracle.median(f, k, wmask)[0], f"hist masked median k={k}")
+        say(f"case hist plain median {dt} k={k}")
+        irfilter.ir_filter_median(src, dst, k)
+        torch.cuda.synchronize()
+        assert_same(to_host(dst), oracle.median(f, k)[0], f"hist median filter k={k}")
 
 
 def test_two_passes_and_stack(dev):

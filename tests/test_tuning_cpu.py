@@ -32,20 +32,21 @@ def _restore_defaults():
 
 def test_defaults():
     for dt in ("u8", "u16"):
-        for k in (3, 5, 9, 11, 13, 15):
+        for k in (3, 9, 11, 13, 15):
             assert irfilter.get_tuning(dt, k) == (128, irfilter.IRF_SELECT_NETWORK)
-        assert irfilter.get_tuning(dt, 7) == (256, irfilter.IRF_SELECT_NETWORK)
+        for k in (5, 7):
+            assert irfilter.get_tuning(dt, k) == (256, irfilter.IRF_SELECT_NETWORK)
         for k in range(17, 32, 2):
             assert irfilter.get_tuning(dt, k) == (256, irfilter.IRF_SELECT_GROUP)
     assert irfilter.get_batch_threads() == 128
 
 
 def test_set_get_and_restore():
-    irfilter.set_tuning("u16", 5, 256, irfilter.IRF_SELECT_BISECT)
-    assert irfilter.get_tuning("u16", 5) == (256, irfilter.IRF_SELECT_BISECT)
-    assert irfilter.get_tuning("u8", 5) == (128, irfilter.IRF_SELECT_NETWORK)  # per pixel type
+    irfilter.set_tuning("u16", 5, 128, irfilter.IRF_SELECT_BISECT)
+    assert irfilter.get_tuning("u16", 5) == (128, irfilter.IRF_SELECT_BISECT)
+    assert irfilter.get_tuning("u8", 5) == (256, irfilter.IRF_SELECT_NETWORK)  # per pixel type
     irfilter.set_tuning("u16", 5, 0, 0)
-    assert irfilter.get_tuning("u16", 5) == (128, irfilter.IRF_SELECT_NETWORK)
+    assert irfilter.get_tuning("u16", 5) == (256, irfilter.IRF_SELECT_NETWORK)
 
 
 @pytest.mark.parametrize("args,status", [
@@ -190,6 +191,14 @@ def test_candidates_cover_every_available_kernel():
         assert (128, irfilter.IRF_SELECT_NETWORK) in c and (256, irfilter.IRF_SELECT_BISECT) in c
         assert len(c) == 4
     for k in autotune.LARGE_WINDOWS:
-        assert autotune.candidates(k) == [(128, irfilter.IRF_SELECT_GROUP), (256, irfilter.IRF_SELECT_GROUP)]
-        irfilter.set_tuning("u8", k, 256, irfilter.IRF_SELECT_GROUP)
-        assert irfilter.get_tuning("u8", k) == (256, irfilter.IRF_SELECT_GROUP)
+        assert sorted(autotune.candidates(k)) == sorted(
+            [(t, s) for t in (128, 256) for s in (irfilter.IRF_SELECT_GROUP, irfilter.IRF_SELECT_HIST)])
+        for t, s in autotune.candidates(k):
+            irfilter.set_tuning("u8", k, t, s)
+            assert irfilter.get_tuning("u8", k) == (t, s)
+        irfilter.set_tuning("u8", k, 0, 0)
+        # networks and one-lane bisection do not exist above 15x15, the radix select not below
+        with pytest.raises(irfilter.IrfError):
+            irfilter.set_tuning("u8", k, 256, irfilter.IRF_SELECT_NETWORK)
+    with pytest.raises(irfilter.IrfError):
+        irfilter.set_tuning("u16", 15, 256, irfilter.IRF_SELECT_HIST)

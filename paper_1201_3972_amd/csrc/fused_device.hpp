@@ -79,7 +79,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
             for (int q = 0; q < R; ++q)
                 *reinterpret_cast<uint2 *>(sm.tile + centre0 + q * G::pitch) = make_uint2(o1[q][0], o1[q][1]);
         } else {
-            median_into_tile<K, NT, SEL, true>(sm, f1, centre0, t, a.pk_one);
+            median_into_tile<K, NT, SEL, G::tile_px, true>(sm, f1, centre0, t, a.pk_one);
         }
         if (tid == 0) sm.count = 0;  // every thread read the pass-1 list length before its selection
         __syncthreads();
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
         if constexpr (K == 3) {
             dense3_block<R>(sm.tile, strip, tx, f2, o2);
         } else {
-            median_into_tile<K, NT, SEL, true>(sm, f2, centre0, t, a.pk_one);
+            median_into_tile<K, NT, SEL, G::tile_px, true>(sm, f2, centre0, t, a.pk_one);
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const uint2 c = *reinterpret_cast<const uint2 *>(sm.tile + centre0 + q * G::pitch);

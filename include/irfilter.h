@@ -352,13 +352,12 @@ irf_status ir_filter_set_tuning(irf_dtype dtype, int window, int threads, int se
  *            256, 512  fused, workgroups of that size (blocks of 128x64 or
  *                      128x128 pixels, of which 120 x (64 or 128 - window + 1)
  *                      are output; the rest is recomputed by neighbours)
- *            -1        automatic, the default: per call, the fused size whose
- *                      tiles cover the fewest pixels if they cover no more than
- *                      the tiles of two separate passes (at 3x3: fewer), else
- *                      separate passes (both kernels are bound by ALU work per
- *                      covered pixel, so fusion pays where its overlap costs
- *                      nothing: 320x240 frames fuse from 5x5 up, 640x512 and
- *                      1920x1080 frames do not)
+ *            -1        automatic, the default: separate passes.  Both kernels
+ *                      are bound by ALU work per covered pixel; the fused
+ *                      tiling never covers fewer pixels than two single passes,
+ *                      and at equal coverage separate passes measured faster
+ *                      at every window up to 9x9.  The autotuner sets a fused
+ *                      size where it measures one faster.
  * Fused kernels exist for windows up to 9x9 (IRF_ERR_TUNING otherwise; -1
  * and 0 are accepted for every window).  The table is process-wide like the
  * one above. */

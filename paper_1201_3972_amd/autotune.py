@@ -31,7 +31,7 @@ from . import irfilter
 PKG = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(PKG, "tuning")
 WINDOWS = (3, 5, 7, 9, 11, 13, 15)
-LARGE_WINDOWS = (17, 19, 21, 23, 25, 27, 29, 31)  # group bisection only: workgroup size is the choice
+LARGE_WINDOWS = (17, 19, 21, 23, 25, 27, 29, 31)  # group bisection or the radix select
 SELECT_BY_NAME = {name: code for code, name in irfilter.SELECT_NAMES.items()}
 NETWORK_MAX_WINDOW = 15
 FUSED_MAX_WINDOW = 9

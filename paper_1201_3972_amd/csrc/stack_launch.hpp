@@ -50,33 +50,15 @@ inline int fused_tile_rows(int window, int threads) {
 }
 // Fusion setting that picks per frame size (the untuned default).
 constexpr int kFusionAuto = -1;
-// The automatic choice for a W x H frame whose single passes run with
-// plain_threads: the fused workgroup size whose tiles cover the fewest pixels,
-// if they cover no more than the plain tiles of two separate passes (at 3x3:
-// fewer), else 0.
-// Both kernels are bound by vector ALU work per covered pixel, so fusion only
-// pays where its overlapping tiles cost no extra work (6 fused tiles of 120
-// output columns cover a 640-pixel row that 5 plain tiles cover, for one).
-inline int auto_fusion(int width, int height, int window, int plain_threads) {
-    if (window > kFusedMaxWindow) return 0;
-    auto cdiv = [](long long a, long long b) { return (a + b - 1) / b; };
-    const long long ph = plain_threads / kThreadsX * Geometry<3>::R;
-    const long long plain = 2 * cdiv(width, kTileW) * cdiv(height, ph) * kTileW * ph;
-    // at 3x3 both forms compute every median in registers and separate passes
-    // win at equal coverage; larger windows fuse at equal coverage
-    const bool strict = window == 3;
-    int best = 0;
-    long long best_px = plain;
-    for (int t : {256, 512}) {
-        const long long th = t / kThreadsX * Geometry<3>::R;
-        const long long px = 2 * cdiv(width, kFusedTileW) * cdiv(height, fused_tile_rows(window, t)) * kTileW * th;
-        if (px < best_px || (px == best_px && best == 0 && !strict)) {
-            best = t;
-            best_px = px;
-        }
-    }
-    return best;
-}
+// The automatic choice (the default): separate passes.  Both kernels are
+// bound by vector ALU work per covered pixel, and a fused block outputs only
+// 120 x (TH - k + 1) of its 128 x TH pixels, so its tiling never covers fewer
+// pixels than the tiles of two single passes (6 fused tiles cover a 640-pixel
+// row that 5 plain tiles cover, for one); at equal coverage separate passes
+// measured faster at every window 3x3 to 9x9 (320x240 u8 and 640x512 u16
+// stacks).  The fused kernels run when set explicitly, or when the autotuner
+// finds one faster on the caller's frames.
+inline int auto_fusion(int /*width*/, int /*height*/, int /*window*/, int /*plain_threads*/) { return 0; }
 // Launch the fused kernel for a.total_tiles fused tiles (the caller sets the
 // tile counts from kFusedTileW and fused_tile_rows); false if no kernel exists.
 bool launch_fused2(int bytes, int window, int threads, const StackArgs &a, hipStream_t s);

@@ -323,7 +323,7 @@ FUSION_AUTO = -1
 
 def get_fusion(dtype, window: int) -> int:
     """Fusion setting of (dtype, window): the fused kernel's workgroup size,
-    0 for separate launches, or FUSION_AUTO (chosen per frame size)."""
+    0 for separate launches, or FUSION_AUTO (the library's automatic choice)."""
     t = ctypes.c_int()
     _check("ir_filter_get_fusion", load().ir_filter_get_fusion(_dtype_arg(dtype), window, ctypes.byref(t)))
     return t.value
@@ -340,7 +340,8 @@ def resolve_fusion(dtype, window: int, width: int, height: int) -> int:
 
 def set_fusion(dtype, window: int, threads: int) -> None:
     """Fuse pairs of passes with workgroups of `threads` (256 or 512), run
-    passes separately (0), or choose per frame size (FUSION_AUTO, the default)."""
+    passes separately (0), or leave it to the library (FUSION_AUTO, the default,
+    which runs separate passes)."""
     _check("ir_filter_set_fusion", load().ir_filter_set_fusion(_dtype_arg(dtype), window, threads))
 
 

@@ -83,3 +83,19 @@ def test_dense_flags_plain_median_and_stack(dev, k):
     for i in range(3):
         assert np.array_equal(out[i, :, :270], oracle.median(f[i], k)[0]), i
     assert (out[:, :, 270:] == 0x5a5a).all()  # row padding untouched
+
+
+@pytest.mark.parametrize("dt", ["u8", "u16"])
+def test_dense_caller_mask(dev, dt):
+    # the masked median with a caller mask that marks about 70 % of the pixels
+    rng = np.random.default_rng(77 + (dt == "u16"))
+    hi = 256 if dt == "u8" else 1 << 14
+    f = rng.integers(0, hi, size=(150, 261)).astype(np.uint8 if dt == "u8" else np.uint16)
+    mask = (rng.random(f.shape) < 0.7).astype(np.uint8)
+    src = to_dev(torch, f, dev)
+    m = torch.from_numpy(mask).to(dev)
+    dst = torch.empty_like(src)
+    say(f"case overflow caller mask {dt} k=5")
+    irfilter.ir_filter_median(src, dst, 5, mask=m)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(torch, dst), oracle.median(f, 5, mask)[0])

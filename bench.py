@@ -381,7 +381,8 @@ def section_c5(torch, serving, oracle, dev, duration: float = 3.0) -> dict:
     offered 2x to 25x faster.  Every served result (each request's output in
     pinned host memory) is compared with the oracle's output for its frame and
     window.  The sustained rate is the highest offered rate whose p99 latency
-    stays within one frame period (33.3 ms)."""
+    (over the whole run) stays within one frame period (33.3 ms); each run
+    starts on a device kept busy for the quarter second before it."""
     import hashlib
     out = {"workload": "32 x 640x512 u16 streams at 30 fps (exponential inter-arrival) + 5% 3840x2160 u16 "
                        "frames, windows 3/5/7/9, 512 MiB arena for one-off frames, results in pinned host memory",
@@ -389,14 +390,30 @@ def section_c5(torch, serving, oracle, dev, duration: float = 3.0) -> dict:
     cache = {}  # (frame content hash, window) -> oracle output
     checked = 0
     sustained = None
-    for scale, dur in ((1.0, duration), (2.0, 1.5), (5.0, 1.0), (10.0, 0.5), (14.0, 0.5), (17.0, 0.5),
-                       (20.0, 0.5), (25.0, 0.4)):
+    # the device is kept busy for a quarter second right before each run: the
+    # host work between runs (workload set-up, the parity check) leaves it idle
+    # for seconds, and its clocks then need some 30 launches to recover, which
+    # at high load builds a backlog that takes longer than a short run to drain
+    from paper_1201_3972_amd import irfilter
+    warm_src = torch.zeros((64, 512, 640), dtype=torch.int16, device=dev).view(torch.uint16)
+    warm_dst = torch.empty_like(warm_src)
+
+    def warm():
+        t_w = time.perf_counter()
+        while time.perf_counter() - t_w < 0.25:
+            for _ in range(10):
+                irfilter.ir_filter_run_frames(warm_src, warm_dst, 5)
+            torch.cuda.synchronize()
+
+    for scale, dur in ((1.0, duration), (2.0, 1.5), (5.0, 1.0), (10.0, 1.0), (14.0, 1.0), (17.0, 1.0),
+                       (20.0, 1.0), (25.0, 0.6)):
         streams, reqs = serving.video_workload(torch, seed=77, duration=dur, rate_scale=scale)
         srv = serving.Server(memory_budget=512 << 20, max_inflight=3)
         for st in streams:
             srv.register_stream(st.stream_id, st.width, st.height, st.dtype)
         for r in reqs:
             srv.submit(r)
+        warm()
         t1 = time.perf_counter()
         srv.run_until_idle()
         wall = time.perf_counter() - t1
@@ -423,6 +440,8 @@ def section_c5(torch, serving, oracle, dev, duration: float = 3.0) -> dict:
                                    f"{scale}x the offered load")
         checked += len(reqs)
         rep = serving.summarize(reqs, wall)
+        late = [r.latency * 1e3 for r in reqs if r.latency is not None and r.arrival >= 0.2]
+        rep["p99_ms_after_first_0p2s"] = round(float(np.percentile(late, 99)), 3) if late else None
         rep["batches"] = steps
         rep["mean_batch"] = round(len(reqs) / max(steps, 1), 2)
         rep["large_frames"] = sum(1 for r in reqs if r.shape[0] == 2160)

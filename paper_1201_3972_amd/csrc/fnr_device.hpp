@@ -139,6 +139,42 @@ __device__ __forceinline__ uint32_t shift_pair(uint32_t hi_word, uint32_t lo_wor
     return __builtin_amdgcn_alignbyte(hi_word, lo_word, 2);
 }
 
+// Three-input min / max of packed pairs for tiles whose values are all below
+// 0x4000 (every 8-bit frame, and 14-bit data).  Read as IEEE half-precision
+// bit patterns such values are positive and finite (normal or subnormal) and
+// order exactly like the integers, and the packed half-precision minimum3 /
+// maximum3 of gfx950 returns one of its inputs bit for bit (the kernels keep
+// half-precision subnormals: no flushing), so one instruction does the work of
+// two packed integer min / max.  Each is written as the one instruction (an
+// ALU operation on registers): built from two-input minimum intrinsics, the
+// compiler shares common sub-minima between neighbouring groups and emits
+// three-input instructions with a repeated operand, which saves nothing.
+__device__ __forceinline__ uint32_t h_min3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_pk_minimum3_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+__device__ __forceinline__ uint32_t h_max3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_pk_maximum3_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+// (min(a.lo, a.hi, p.lo), min(a.lo, a.hi, p.hi)), and the same for max: the
+// second operand is a with its halves swapped (op_sel)
+__device__ __forceinline__ uint32_t h_min_both(uint32_t a, uint32_t p) {
+    uint32_t r;
+    asm("v_pk_minimum3_f16 %0, %1, %1, %2 op_sel:[0,1,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(p));
+    return r;
+}
+__device__ __forceinline__ uint32_t h_max_both(uint32_t a, uint32_t p) {
+    uint32_t r;
+    asm("v_pk_maximum3_f16 %0, %1, %1, %2 op_sel:[0,1,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(p));
+    return r;
+}
+// Largest value the three-input path takes (exclusive): a tile qualifies when
+// no staged value has either of the top two bits set.
+constexpr uint32_t kF16SafeMask = 0xC000C000u;
+
 // ---------------------------------------------------------------------------
 // 1. tile load
 // ---------------------------------------------------------------------------
@@ -359,8 +395,31 @@ __device__ __forceinline__ void commit_tile(const TileChunks<K, NT> &c, uint16_t
     }
 }
 
+// Whether every value of the thread's chunks lies below 0x4000 (the range of
+// the three-input half-precision detection path).
+template <int K, int NT>
+__device__ __forceinline__ bool chunks_small(const TileChunks<K, NT> &c) {
+    using G = Geometry<K, NT>;
+    using C = TileChunks<K, NT>;
+    const int tid = threadIdx.x;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int j = 0; j < C::kRounds; ++j) {
+        const uint32_t w = c.v[j].x | c.v[j].y | c.v[j].z | c.v[j].w;
+        if (j < C::kRounds - 1 || (tid >> 4) + j * C::kStep < G::rows) acc |= w;
+    }
+#pragma unroll
+    for (int j = 0; j < C::kHRounds; ++j) {
+        const uint32_t w = c.h[j].x | c.h[j].y | c.h[j].z | c.h[j].w;
+        if (tid + j * NT < C::kHalos) acc |= w;
+    }
+    return (acc & kF16SafeMask) == 0;
+}
+
+// Stage the tile; returns whether the values this thread staged all lie below
+// 0x4000 (always for 8-bit frames; callers that do not use it drop the test).
 template <typename T, int K, int NT = kThreads, bool HALF = false, bool EARLY = false>
-__device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
+__device__ __forceinline__ bool load_tile(const uint8_t *src, uint64_t pitch, int W, int H, int x0,
                                           int y0, bool aligned, uint16_t *tile) {
     TileChunks<K, NT> c;
     if constexpr (EARLY) __builtin_amdgcn_s_setprio(3);
@@ -370,6 +429,10 @@ __device__ __forceinline__ void load_tile(const uint8_t *src, uint64_t pitch, in
         __syncthreads();
     }
     commit_tile<K, NT>(c, tile);
+    if constexpr (sizeof(T) == 1)
+        return true;
+    else
+        return chunks_small<K, NT>(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,7 +463,7 @@ __device__ __forceinline__ uint32_t hi_lo(uint32_t a, uint32_t b) {  // (a.hi, b
 // r+1 for column 1, packed into one pair, gives pair 0.  Pair 1 is the same two
 // columns further right, and shares E_-m+1..E_m with pair 0.  No odd-aligned
 // pair is ever formed.
-template <int r>
+template <int r, bool F16 = false>
 __device__ __forceinline__ void row_minmax_odd(const uint16_t *p, uint32_t &mn0, uint32_t &mn1,
                                                uint32_t &mx0, uint32_t &mx1, uint32_t &c0, uint32_t &c1) {
     constexpr int m = (r - 1) / 2;
@@ -415,6 +478,26 @@ __device__ __forceinline__ void row_minmax_odd(const uint16_t *p, uint32_t &mn0,
         D[j + 1] = w.y;
     }
     auto E = [&](int j) -> uint32_t { return D[j - JLO]; };
+    const uint32_t p0 = hi_lo(E(-m - 1), E(m + 1)), p1 = hi_lo(E(-m), E(m + 2));
+    c0 = E(0);
+    c1 = E(1);
+    if constexpr (F16) {
+        // E_-m+1 .. E_m-1 (an odd count) folded in threes, then E_m with each
+        // output pair's own end pair
+        uint32_t smn = E(1 - m), smx = smn;
+#pragma unroll
+        for (int j = 2 - m; j + 1 <= m - 1; j += 2) {
+            smn = h_min3(smn, E(j), E(j + 1));
+            smx = h_max3(smx, E(j), E(j + 1));
+        }
+        const uint32_t a_mn = h_min3(smn, E(m), E(-m)), a_mx = h_max3(smx, E(m), E(-m));
+        const uint32_t b_mn = h_min3(smn, E(m), E(m + 1)), b_mx = h_max3(smx, E(m), E(m + 1));
+        mn0 = h_min_both(a_mn, p0);
+        mx0 = h_max_both(a_mx, p0);
+        mn1 = h_min_both(b_mn, p1);
+        mx1 = h_max_both(b_mx, p1);
+        return;
+    }
     uint32_t a_mn = E(0), a_mx = E(0), b_mn = E(1), b_mx = E(1);
     if constexpr (m > 0) {
         uint32_t smn = E(1 - m), smx = smn;  // E_-m+1 .. E_m, shared by both pairs
@@ -428,22 +511,19 @@ __device__ __forceinline__ void row_minmax_odd(const uint16_t *p, uint32_t &mn0,
         b_mn = pk_min(smn, E(m + 1));
         b_mx = pk_max(smx, E(m + 1));
     }
-    const uint32_t p0 = hi_lo(E(-m - 1), E(m + 1)), p1 = hi_lo(E(-m), E(m + 2));
     mn0 = pk_min(both_min(a_mn), p0);
     mx0 = pk_max(both_max(a_mx), p0);
     mn1 = pk_min(both_min(b_mn), p1);
     mx1 = pk_max(both_max(b_mx), p1);
-    c0 = E(0);
-    c1 = E(1);
 }
 
 // Even radius and 3x3: the shared middle offsets with odd-aligned pairs built by
 // byte alignment (at 3x3 this measured faster than the odd-radius form).
-template <int r>
+template <int r, bool F16 = false>
 __device__ __forceinline__ void row_minmax(const uint16_t *p, uint32_t &mn0, uint32_t &mn1,
                                            uint32_t &mx0, uint32_t &mx1, uint32_t &c0, uint32_t &c1) {
     if constexpr ((r & 1) && r >= 3) {
-        row_minmax_odd<r>(p, mn0, mn1, mx0, mx1, c0, c1);
+        row_minmax_odd<r, F16>(p, mn0, mn1, mx0, mx1, c0, c1);
         return;
     }
     // pairs JLO..JHI cover columns -r .. 3+r; the range is widened to whole
@@ -466,19 +546,33 @@ __device__ __forceinline__ void row_minmax(const uint16_t *p, uint32_t &mn0, uin
     };
     // pair 0 needs offsets -r..r, pair 1 needs 2-r..r+2; share 2-r..r
     uint32_t smin = V(2 - r), smax = smin;
+    uint32_t a = V(-r), b = V(1 - r), c = V(r + 1), d = V(r + 2);
+    c0 = D[0 - JLO];
+    c1 = D[1 - JLO];
+    if constexpr (F16) {
+        // 2r - 2 shared offsets after the first, folded in threes
+#pragma unroll
+        for (int o = 3 - r; o + 1 <= r; o += 2) {
+            const uint32_t v = V(o), w = V(o + 1);
+            smin = h_min3(smin, v, w);
+            smax = h_max3(smax, v, w);
+        }
+        mn0 = h_min3(smin, a, b);
+        mx0 = h_max3(smax, a, b);
+        mn1 = h_min3(smin, c, d);
+        mx1 = h_max3(smax, c, d);
+        return;
+    }
 #pragma unroll
     for (int o = 3 - r; o <= r; ++o) {
         uint32_t v = V(o);
         smin = pk_min(smin, v);
         smax = pk_max(smax, v);
     }
-    uint32_t a = V(-r), b = V(1 - r), c = V(r + 1), d = V(r + 2);
     mn0 = pk_min(smin, pk_min(a, b));
     mx0 = pk_max(smax, pk_max(a, b));
     mn1 = pk_min(smin, pk_min(c, d));
     mx1 = pk_max(smax, pk_max(c, d));
-    c0 = D[0 - JLO];
-    c1 = D[1 - JLO];
 }
 
 // Flag bit layout inside a thread's 32-bit mask: bit q (+0, +16, +8, +24) is
@@ -494,7 +588,7 @@ __device__ __forceinline__ int bit_row(int b) { return b & 7; }
 // suffixes are formed when its last row arrives, prefixes run as rows arrive,
 // and every output row is turned into flag bits as soon as both parts exist, so
 // only about one block of horizontal results is live at a time.
-template <int K>
+template <int K, bool F16 = false>
 __device__ __forceinline__ uint32_t detect_block_blocks(const uint16_t *tile, int strip, int tx,
                                                         uint32_t pk_one) {
     using G = Geometry<K>;
@@ -517,7 +611,7 @@ __device__ __forceinline__ uint32_t detect_block_blocks(const uint16_t *tile, in
         constexpr int i = decltype(ic)::value;
         constexpr int blk = i / K, first = blk * K;
         uint32_t a, b;
-        row_minmax<G::r>(base + i * G::pitch, mn0[i], mn1[i], mx0[i], mx1[i], a, b);
+        row_minmax<G::r, F16>(base + i * G::pitch, mn0[i], mn1[i], mx0[i], mx1[i], a, b);
         if constexpr (i >= G::r && i < G::r + R) {
             c0[i - G::r] = a;
             c1[i - G::r] = b;
@@ -534,8 +628,13 @@ __device__ __forceinline__ uint32_t detect_block_blocks(const uint16_t *tile, in
         if constexpr (o >= 0 && o < R && o % K != 0)
             emit(o, pk_min(mn0[o], pmn0[i]), pk_min(mn1[o], pmn1[i]), pk_max(mx0[o], pmx0[i]),
                  pk_max(mx1[o], pmx1[i]));
-        // block complete: suffixes in place, and the output that starts the block
-        if constexpr (i % K == K - 1 || i == L - 1) {
+        // block complete: suffixes in place, and the output that starts the
+        // block.  The last block has no block after it, so no output straddles
+        // out of it: its one output (when it starts one) takes the running
+        // prefix, which already spans the whole block.
+        if constexpr (i == L - 1 && i - first == K - 1) {
+            if constexpr (first < R) emit(first, pmn0[i], pmn1[i], pmx0[i], pmx1[i]);
+        } else if constexpr (i % K == K - 1 || i == L - 1) {
             static_for(std::make_integer_sequence<int, i - first>{}, [&](auto jc) {
                 constexpr int j = i - 1 - decltype(jc)::value;
                 mn0[j] = pk_min(mn0[j], mn0[j + 1]); mn1[j] = pk_min(mn1[j], mn1[j + 1]);
@@ -552,7 +651,7 @@ __device__ __forceinline__ uint32_t detect_block_blocks(const uint16_t *tile, in
 // [R-1, K) lie in every output row's window (the core, reduced as it streams
 // by); output row o also needs the suffix of rows [o, R-1) and the prefix of
 // rows [K, o+K).  Only the R-1 rows before the core are held.
-template <int K>
+template <int K, bool F16 = false>
 __device__ __forceinline__ uint32_t detect_block_core(const uint16_t *tile, int strip, int tx,
                                                       uint32_t pk_one) {
     using G = Geometry<K>;
@@ -574,7 +673,7 @@ __device__ __forceinline__ uint32_t detect_block_core(const uint16_t *tile, int 
     static_for(std::make_integer_sequence<int, L>{}, [&](auto ic) {
         constexpr int i = decltype(ic)::value;
         uint32_t a0, a1, b0, b1, ca, cb;
-        row_minmax<G::r>(base + i * G::pitch, a0, a1, b0, b1, ca, cb);
+        row_minmax<G::r, F16>(base + i * G::pitch, a0, a1, b0, b1, ca, cb);
         if constexpr (i >= G::r && i < G::r + R) {
             c0[i - G::r] = ca;
             c1[i - G::r] = cb;
@@ -617,13 +716,13 @@ __device__ __forceinline__ uint32_t detect_block_core(const uint16_t *tile, int 
     return flags;
 }
 
-template <int K>
+template <int K, bool F16 = false>
 __device__ __forceinline__ uint32_t detect_block(const uint16_t *tile, int strip, int tx,
                                                  uint32_t pk_one) {
     if constexpr (K > Geometry<K>::R)
-        return detect_block_core<K>(tile, strip, tx, pk_one);
+        return detect_block_core<K, F16>(tile, strip, tx, pk_one);
     else
-        return detect_block_blocks<K>(tile, strip, tx, pk_one);
+        return detect_block_blocks<K, F16>(tile, strip, tx, pk_one);
 }
 
 // Flags of the opt-in directional detector for the thread's 4 x R block (not
@@ -1244,6 +1343,9 @@ struct TileSmem {
     uint16_t tile[G::rows * G::pitch];
     uint16_t list[LIST];  // LDS offsets of flagged centres, then their medians
     uint32_t count;       // list length
+    // per wave: nonzero if the wave staged a value of 0x4000 or more (the
+    // tile then takes the integer detection path)
+    alignas(8) uint8_t large[8];
     HistSpace<NT, SEL == kSelectHist> hist;
 };
 
@@ -1469,9 +1571,14 @@ __device__ __forceinline__ uint32_t median_into_tile(SmemFor<K, NT, SEL, LIST> &
 // workgroups' detection, which fills the gaps; with the loads also issued at
 // the highest priority (load_tile, EARLY), this measured 9-12% faster at 5x5
 // to 9x9.
+//
+// F16 (uniform): every staged value of the tile lies below 0x4000, so the
+// detection's horizontal pass may use the three-input half-precision min / max
+// (same flags, fewer instructions).
 template <typename T, int K, int MODE, int NT = kThreads, int SEL = default_select(K), bool PRIO = false,
           int LIST = Geometry<K, NT>::tile_px>
-__device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, SmemFor<K, NT, SEL, LIST> &sm) {
+__device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, SmemFor<K, NT, SEL, LIST> &sm,
+                                                 bool f16 = false) {
     using G = Geometry<K, NT>;
     static_assert(((SEL == kSelectGroup || SEL == kSelectHist) && K > kNetworkMaxWindow) ||
                       (K <= kNetworkMaxWindow && (SEL == kSelectBisect || SEL == kSelectNetwork)),
@@ -1491,7 +1598,9 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, S
 
     uint32_t flags;
     if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR) {
-        flags = detect_block<K>(sm.tile, strip, tx, a.pk_one) & valid;
+        flags = (f16 ? detect_block<K, true>(sm.tile, strip, tx, a.pk_one)
+                     : detect_block<K, false>(sm.tile, strip, tx, a.pk_one)) &
+                valid;
     } else if constexpr (MODE == MODE_DETECT_DIR) {
         flags = directional_block<K>(sm.tile, strip, tx, a.pk_one) & valid;
     } else if constexpr (MODE == MODE_MEDIAN_MASK) {
@@ -1596,13 +1705,21 @@ __device__ __forceinline__ void tile_origin(const StackArgs &a, int tile, int th
 // complete and after the selection.  Other resident workgroups run while one
 // waits for its tile's loads; wave priorities favour every phase but
 // detection (process_tile).
+// Occupancy target of the stack kernel: the 5x5 FNR kernel holds six waves per
+// SIMD (its LDS allows six 256-thread workgroups per CU; without the hint its
+// two detection paths take 96 VGPRs and five waves: 2% slower); the others
+// take what their registers and LDS give.
+constexpr int stack_waves(int K, int MODE) { return K == 5 && MODE == MODE_FNR ? 6 : 1; }
+
 template <typename T, int K, int MODE, int NT, int SEL>
-__global__ __launch_bounds__(NT) void fnr_persistent_kernel(StackArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stack_waves(K, MODE)))) void fnr_persistent_kernel(
+    StackArgs a) {
     using G = Geometry<K, NT>;
     // the modes that select (K > 3: 3 x 3 computes every median in registers)
     // use the short list; detection has none to speak of
     constexpr bool kSelects = K > 3 && MODE != MODE_DETECT && MODE != MODE_DETECT_DIR;
     constexpr int LIST = kSelects ? stack_list(K, G::tile_px) : 2;
+    constexpr bool kDetects = MODE == MODE_DETECT || MODE == MODE_FNR;  // min / max detection
     __shared__ __attribute__((aligned(16))) SmemFor<K, NT, SEL, LIST> sm;
     const TileRange rg = xcd_range(blockIdx.x, gridDim.x, a.total_tiles);
     const bool aligned = a.aligned != 0;
@@ -1615,11 +1732,23 @@ __global__ __launch_bounds__(NT) void fnr_persistent_kernel(StackArgs a) {
         int f, x0, y0;
         tile_origin(a, t, G::TH, f, x0, y0);
         // includes the barrier after which the previous tile is no longer read
-        load_tile<T, K, NT, false, true>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, a.width, a.height,
-                                         x0, y0, aligned, sm.tile);
+        const bool small = load_tile<T, K, NT, false, true>(a.src + (uint64_t)f * a.src_stride, a.src_pitch,
+                                                            a.width, a.height, x0, y0, aligned, sm.tile);
+        if constexpr (kDetects) {
+            // each wave reports whether it staged a large value; every wave
+            // writes its own slot, read after the barrier below
+            const bool wave_large = __builtin_amdgcn_ballot_w64(!small) != 0;
+            if ((threadIdx.x & 63) == 0) sm.large[threadIdx.x >> 6] = wave_large ? 1 : 0;
+        }
         if (threadIdx.x == 0) sm.count = 0;
         __syncthreads();
-        flagged += process_tile<T, K, MODE, NT, SEL, true, LIST>(a, t, sm);
+        bool f16 = false;
+        if constexpr (kDetects) {
+            uint64_t any = 0;
+            __builtin_memcpy(&any, sm.large, NT / 64);
+            f16 = __builtin_amdgcn_readfirstlane((uint32_t)(any | (any >> 32))) == 0;
+        }
+        flagged += process_tile<T, K, MODE, NT, SEL, true, LIST>(a, t, sm, f16);
     }
     if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR || MODE == MODE_DETECT_DIR) {
         if (a.count != nullptr && (threadIdx.x & 63) == 0 && flagged != 0)

@@ -572,13 +572,14 @@ def section_f1(torch, irfilter, synth, oracle, dev, rounds: int = 5, reps: int =
 
 
 def section_f2(torch, irfilter, synth, oracle, dev, frames: int = 8, reps: int = 3) -> dict:
-    """Windows above 15x15 (17x17 .. 31x31) on a stack of 1920x1080 u16 frames
-    with 40 % mixed impulses, 15x15 (networks) beside them: ms per frame for
-    each selection of the large windows (lane-group bisection and the
-    histogram radix select), 256-thread workgroups.  Parity: a whole 480x270 frame of the same recipe against the
-    oracle, and 512 sampled pixels of the timed stack against the oracle's
-    pointwise evaluation."""
-    windows = (15, 17, 19, 21, 23, 25, 27, 29, 31)
+    """Windows above 15x15 (17x17 .. 31x31, and 33x33 .. 63x63 in steps) on a
+    stack of 1920x1080 u16 frames with 40 % mixed impulses, 15x15 (networks)
+    beside them: ms per frame for each selection of the large windows
+    (lane-group bisection and, up to 31x31, the histogram radix select),
+    256-thread workgroups up to 31x31 and 128 above.  Parity: a whole 480x270
+    frame of the same recipe against the oracle, and 512 sampled pixels of the
+    timed stack against the oracle's pointwise evaluation."""
+    windows = (15, 17, 19, 21, 23, 25, 27, 29, 31, 33, 41, 51, 63)
     f = synth.make_frame(synth.c3_spec(0))
     small = synth.make_frame(synth.FrameSpec(480, 270, "u16", "mixed", 0.40, 20.0, synth.config_seed(8)))
     H, W = f.shape
@@ -599,12 +600,13 @@ def section_f2(torch, irfilter, synth, oracle, dev, frames: int = 8, reps: int =
                      "pointwise result", "windows": {}}
     for k in windows:
         sels = ([irfilter.IRF_SELECT_NETWORK] if k <= 15 else
-                [irfilter.IRF_SELECT_GROUP, irfilter.IRF_SELECT_HIST])
+                [irfilter.IRF_SELECT_GROUP, irfilter.IRF_SELECT_HIST] if k <= 31 else [irfilter.IRF_SELECT_GROUP])
+        threads = 256 if k <= 31 else 128
         before = irfilter.get_tuning("u16", k)
         ent = {}
         try:
             for sel in sels:
-                irfilter.set_tuning("u16", k, 256, sel)
+                irfilter.set_tuning("u16", k, threads, sel)
                 irfilter.ir_filter_run(s_src, s_dst, k, flagged_count=cnt)
                 torch.cuda.synchronize()
                 want, wc = oracle.fnr(small, k)
@@ -627,7 +629,7 @@ def section_f2(torch, irfilter, synth, oracle, dev, frames: int = 8, reps: int =
                                                    "flagged_fraction": round(flagged / (frames * W * H), 4)}
         finally:
             irfilter.set_tuning("u16", k, *before)
-        out["windows"][str(k)] = {"threads": 256, **ent}
+        out["windows"][str(k)] = {"threads": threads, **ent}
         if len(ent) > 1:
             out["windows"][str(k)]["faster"] = min(ent, key=lambda n: ent[n]["ms_per_frame"])
         log(f"f2 {k}x{k}: {out['windows'][str(k)]}")

@@ -70,9 +70,9 @@ typedef enum {
 } irf_status;
 
 #define IRF_MAX_DIM 32768
-/* Every entry point takes windows up to 31x31 (batch plans and the server
- * included). */
-#define IRF_MAX_WINDOW 31
+/* The single-frame and stack entry points take windows up to 63x63, batch
+ * plans and the server up to 31x31. */
+#define IRF_MAX_WINDOW 63
 #define IRF_MAX_BATCH_WINDOW 31
 #define IRF_MAX_PASSES 16
 
@@ -327,12 +327,13 @@ void ir_filter_server_destroy(irf_server *server);
  *   IRF_SELECT_NETWORK  forgetful selection networks, two windows per lane
  *                       (windows up to 15x15)
  *   IRF_SELECT_BISECT   grey-level bisection, one window per lane (up to 15x15)
- *   IRF_SELECT_GROUP    grey-level bisection, one window per group of 4, 8 or
- *                       16 lanes (above 15x15)
+ *   IRF_SELECT_GROUP    grey-level bisection, one window per group of 4, 8,
+ *                       16 or 32 lanes (above 15x15; above 31x31 the only
+ *                       choice, with 128 threads)
  *   IRF_SELECT_HIST     two-pass radix select over a 256-bin LDS histogram,
- *                       one window per group of 16 lanes (above 15x15)
- * Untuned defaults: 256 threads for 5x5, 7x7 and above 15x15, else 128; networks
- * up to 15x15, group bisection above.
+ *                       one window per group of 16 lanes (17x17 to 31x31)
+ * Untuned defaults: 256 threads for 5x5, 7x7 and 17x17 to 31x31, else 128;
+ * networks up to 15x15, group bisection above.
  * ir_filter_set_tuning(dtype, window, 0, 0)
  * restores the default; an unavailable combination returns IRF_ERR_TUNING.
  * The autotuner of the Python package measures the choices and sets them.

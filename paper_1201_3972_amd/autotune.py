@@ -32,6 +32,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 TUNING_DIR = os.path.join(PKG, "tuning")
 WINDOWS = (3, 5, 7, 9, 11, 13, 15)
 LARGE_WINDOWS = (17, 19, 21, 23, 25, 27, 29, 31)  # group bisection or the radix select
+# above 31x31 one kernel per window (group bisection, 128 threads): nothing to tune
+LARGE_MAX_WINDOW = 31
 SELECT_BY_NAME = {name: code for code, name in irfilter.SELECT_NAMES.items()}
 NETWORK_MAX_WINDOW = 15
 FUSED_MAX_WINDOW = 9
@@ -42,7 +44,9 @@ FUSION_MARGIN = 1.03  # a fixed fusion choice replaces the automatic one only if
 def candidates(window: int) -> List[Tuple[int, int]]:
     """Every (threads, select) with a kernel for this window: networks and
     one-lane bisection up to 15x15, group bisection and the histogram radix
-    select above."""
+    select up to 31x31, group bisection on 128 threads above."""
+    if window > LARGE_MAX_WINDOW:
+        return [(128, irfilter.IRF_SELECT_GROUP)]
     if window <= NETWORK_MAX_WINDOW:
         sels = [irfilter.IRF_SELECT_NETWORK, irfilter.IRF_SELECT_BISECT]
     else:

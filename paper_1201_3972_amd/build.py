@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB_PATH = os.path.join(PKG, "libirfilter.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 SOURCES = [os.path.join(CSRC, n) for n in ("batch_cl_a.hip", "batch_cl_b.hip", "stack_u16.hip", "stack_u8.hip",
-                                          "stack_large_u16.hip", "stack_large_u8.hip", "batch_c0.hip",
+                                          "stack_large_u16.hip", "stack_large_u8.hip", "stack_huge_u16.hip",
+                                          "stack_huge_u8.hip", "batch_c0.hip",
                                           "batch_c1.hip", "batch.hip", "irfilter.hip", "server.hip", "fused.hip")]
 ARCH = os.environ.get("IRF_OFFLOAD_ARCH", "gfx950")
 

@@ -79,13 +79,15 @@ __device__ __forceinline__ uint32_t batch_tile(const FrameDesc &d, int local, un
     a.pk_one = pk_one;
     int f, x0, y0;
     tile_origin(a, local, G::TH, f, x0, y0);
-    load_tile<T, K, NT, false, true>(a.src, a.src_pitch, a.width, a.height, x0, y0, a.aligned != 0, sm.tile);
+    const bool small = load_tile<T, K, NT, false, true>(a.src, a.src_pitch, a.width, a.height, x0, y0,
+                                                        a.aligned != 0, sm.tile);
+    post_small(sm.large, small);
     if (threadIdx.x == 0) {
         sm.count = 0;
         *s_next = ticket;  // the loads were waited for, so the atomic has returned too
     }
     __syncthreads();
-    return process_tile<T, K, MODE_FNR, NT, default_select(K), true>(a, local, sm);
+    return process_tile<T, K, MODE_FNR, NT, default_select(K), true>(a, local, sm, tile_small<NT>(sm.large));
 }
 
 // The tile's device code by (pixel type, window) among the class's windows:

@@ -48,23 +48,28 @@ constexpr int kThreadsX = kTileW / 4;        // 32 threads across, 4 columns eac
 constexpr int kStrips = kThreads / kThreadsX;  // 4 strips of R rows
 // Selection algorithm: forgetful selection networks on two windows per lane,
 // grey-level bisection on one window per lane, grey-level bisection on one
-// window per group of 8 or 16 lanes, or a two-pass radix select over LDS
+// window per group of 4 to 32 lanes, or a two-pass radix select over LDS
 // histograms on one window per group of 16 lanes (the last two for windows
-// above 15x15, whose values no longer fit one lane's registers).
+// above 15x15, whose values no longer fit one lane's registers; the radix
+// select up to 31x31).
 enum Select : int { kSelectNetwork = 1, kSelectBisect = 2, kSelectGroup = 3, kSelectHist = 4 };
 constexpr int kNetworkMaxWindow = 15;
 constexpr int kHistLanes = 16;  // lanes per window of the histogram radix select
 constexpr int kHistBins = 256;  // bins of one radix pass
+constexpr int kLargeMaxWindow = 31;  // windows of the radix select, the batch kernels and 256-thread tiles
 // Untuned choices of the stack kernels: 5x5 and 7x7 take 256-thread workgroups
 // on tiles of twice the height, which fill their selection waves better (a
 // 128x32 tile holds about 80 window pairs at 7x7 at the usual impulse rates,
 // just over one wave's worth); the other windows up to 15x15 run faster with
-// the smaller tile, those above (group bisection) with the larger one.
-// Networks beat bisection at every window (by 2.4x at 15x15).  The host's
-// tuning table starts from these and an autotuner may replace them.
-constexpr int default_threads(int K) { return (K == 5 || K == 7 || K > kNetworkMaxWindow) ? 256 : 128; }
+// the smaller tile, those from 17x17 to 31x31 (group bisection) with the
+// larger one; above 31x31 only 128-thread tiles exist.  Networks beat bisection
+// at every window (by 2.4x at 15x15).  The host's tuning table starts from
+// these and an autotuner may replace them.
+constexpr int default_threads(int K) {
+    return (K == 5 || K == 7 || (K > kNetworkMaxWindow && K <= kLargeMaxWindow)) ? 256 : 128;
+}
 constexpr int default_select(int K) { return K <= kNetworkMaxWindow ? kSelectNetwork : kSelectGroup; }
-constexpr int kMaxWindow = 31;
+constexpr int kMaxWindow = 63;
 
 enum Mode : int {
     MODE_DETECT = 0,       // write the noise mask (and count)
@@ -99,15 +104,15 @@ struct Geometry {
     static constexpr int TH = NT / kThreadsX * R;
     static constexpr int rows = TH + 2 * r;  // LDS rows
     static constexpr int tile_px = kTileW * TH;
-    // LDS columns staged left and right of the tile (8 up to 17x17, 16 above),
-    // 8-pixel load chunks per LDS row, and the LDS row pitch in 16-bit values:
-    // 8 values of padding make it 76 (84) dwords, so rows 8 apart (the two
-    // 32-lane halves of a wave during detection) fall on opposite halves of the
-    // 64 banks.
-    static constexpr int halo = r <= 8 ? 8 : 16;
+    // LDS columns staged left and right of the tile (8 up to 17x17, 16 up to
+    // 33x33, 32 above), 8-pixel load chunks per LDS row, and the LDS row pitch
+    // in 16-bit values: 8 values of padding make it 76 (84, 100) dwords, so
+    // rows 8 apart (the two 32-lane halves of a wave during detection) fall on
+    // opposite halves of the 64 banks.
+    static constexpr int halo = r <= 8 ? 8 : r <= 16 ? 16 : 32;
     static constexpr int chunks = (kTileW + 2 * halo) / 8;
     static constexpr int pitch = kTileW + 2 * halo + 8;
-    static_assert(K >= 3 && K <= kMaxWindow && (K & 1), "odd window 3..31");
+    static_assert(K >= 3 && K <= kMaxWindow && (K & 1), "odd window 3..63");
     static_assert(NT % 64 == 0 && NT % kThreadsX == 0, "whole waves of whole thread rows");
     static_assert(r <= halo, "halo must cover the window radius");
     static_assert(rows * pitch <= 65536, "LDS offsets are 16-bit");
@@ -996,34 +1001,41 @@ __device__ __forceinline__ uint32_t median_registers(const uint16_t *w, uint32_t
 }
 
 // One window per group of lanes (windows above 15x15).  The group's L lanes
-// (aligned inside a 16-lane DPP row) hold the window's values g, g + L, g + 2L,
-// ... (S_xy order), two per VGPR, and run the same grey-level bisection as
-// median_registers with counts summed over the group by DPP butterflies.
-// Registers past the window's end repeat its first value, taken back out of
-// every count.  L is the smallest group whose share fits 48 registers (4 lanes
-// at 17x17 and 19x19, 8 up to 27x27, 16 above): each round costs every lane
-// three packed operations per register plus log2(L) butterfly steps, so fewer
-// lanes waste fewer steps, while larger shares cost the kernel occupancy.
+// (aligned inside a 16-lane DPP row, or a 32-lane half of the wave) hold the
+// window's values g, g + L, g + 2L, ... (S_xy order), two per VGPR, and run the
+// same grey-level bisection as median_registers with counts summed over the
+// group by DPP butterflies (and one lane swizzle across the two rows of a
+// 32-lane group).  Registers past the window's end repeat its first value,
+// taken back out of every count.  L is the smallest group whose share fits 48
+// registers (4 lanes at 17x17 and 19x19, 8 up to 27x27, 16 up to 39x39); the
+// windows above take 32 lanes and up to 63 registers each (63x63).  Each round
+// costs every lane three packed operations per register plus log2(L) butterfly
+// steps, so fewer lanes waste fewer steps, while larger shares cost the kernel
+// occupancy.
 template <int K>
 struct GroupPlan {
     static constexpr int N = K * K;
     static constexpr int regs_for(int l) { return (N + 2 * l - 1) / (2 * l); }
-    static constexpr int lanes = regs_for(4) <= 48 ? 4 : regs_for(8) <= 48 ? 8 : 16;
+    static constexpr int lanes = regs_for(4) <= 48 ? 4 : regs_for(8) <= 48 ? 8 : regs_for(16) <= 48 ? 16 : 32;
     static constexpr int regs = regs_for(lanes);  // packed registers per lane
     static constexpr int pad = 2 * lanes * regs - N;                // repeated values in the group
     static_assert(K > lanes, "a lane's next value is at most one window row further");
+    static_assert(regs <= 64, "a lane's share of the window fits 64 registers");
 };
 
-// op over the aligned group of L lanes (L = 4, 8 or 16), result in every lane.
+// op over the aligned group of L lanes (L = 4, 8, 16 or 32), result in every
+// lane.
 template <int L, typename Op>
 __device__ __forceinline__ uint32_t group_reduce(uint32_t v, Op op) {
-    static_assert(L == 4 || L == 8 || L == 16, "groups of 4, 8 or 16 lanes");
+    static_assert(L == 4 || L == 8 || L == 16 || L == 32, "groups of 4, 8, 16 or 32 lanes");
     v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false));   // lane ^ 1
     v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false));   // lane ^ 2
     if constexpr (L >= 8)
         v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));  // 7 - lane in 8
-    if constexpr (L == 16)
+    if constexpr (L >= 16)
         v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));  // 15 - lane
+    if constexpr (L == 32)  // lane ^ 16 (swizzle bit mode: and 0x1f, or 0, xor 0x10)
+        v = op(v, (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F));
     return v;
 }
 
@@ -1705,6 +1717,22 @@ __device__ __forceinline__ void tile_origin(const StackArgs &a, int tile, int th
 // complete and after the selection.  Other resident workgroups run while one
 // waits for its tile's loads; wave priorities favour every phase but
 // detection (process_tile).
+// The tile's detection path, decided by the whole workgroup: each wave posts
+// whether any of its threads staged a value of 0x4000 or more (its own LDS
+// byte, written before the barrier that follows the tile's load; every wave
+// writes its byte for every tile, so nothing needs clearing), and after that
+// barrier every thread reads all the bytes (the same value everywhere).
+__device__ __forceinline__ void post_small(uint8_t *large, bool small) {
+    const bool wave_large = __builtin_amdgcn_ballot_w64(!small) != 0;
+    if ((threadIdx.x & 63) == 0) large[threadIdx.x >> 6] = wave_large ? 1 : 0;
+}
+template <int NT>
+__device__ __forceinline__ bool tile_small(const uint8_t *large) {
+    uint64_t any = 0;
+    __builtin_memcpy(&any, large, NT / 64);
+    return __builtin_amdgcn_readfirstlane((uint32_t)(any | (any >> 32))) == 0;
+}
+
 // Occupancy target of the stack kernel: the 5x5 FNR kernel holds six waves per
 // SIMD (its LDS allows six 256-thread workgroups per CU; without the hint its
 // two detection paths take 96 VGPRs and five waves: 2% slower); the others
@@ -1734,20 +1762,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stack_waves(
         // includes the barrier after which the previous tile is no longer read
         const bool small = load_tile<T, K, NT, false, true>(a.src + (uint64_t)f * a.src_stride, a.src_pitch,
                                                             a.width, a.height, x0, y0, aligned, sm.tile);
-        if constexpr (kDetects) {
-            // each wave reports whether it staged a large value; every wave
-            // writes its own slot, read after the barrier below
-            const bool wave_large = __builtin_amdgcn_ballot_w64(!small) != 0;
-            if ((threadIdx.x & 63) == 0) sm.large[threadIdx.x >> 6] = wave_large ? 1 : 0;
-        }
+        if constexpr (kDetects) post_small(sm.large, small);
         if (threadIdx.x == 0) sm.count = 0;
         __syncthreads();
         bool f16 = false;
-        if constexpr (kDetects) {
-            uint64_t any = 0;
-            __builtin_memcpy(&any, sm.large, NT / 64);
-            f16 = __builtin_amdgcn_readfirstlane((uint32_t)(any | (any >> 32))) == 0;
-        }
+        if constexpr (kDetects) f16 = tile_small<NT>(sm.large);
         flagged += process_tile<T, K, MODE, NT, SEL, true, LIST>(a, t, sm, f16);
     }
     if constexpr (MODE == MODE_DETECT || MODE == MODE_FNR || MODE == MODE_DETECT_DIR) {

@@ -58,16 +58,22 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
         const int ty = rem / a.tiles_x;
         const int ox = (rem - ty * a.tiles_x) * kFusedTileW, oy = ty * OH;
         const int x0 = ox - 4, y0 = oy - r;
-        load_tile<T, K, NT, true, true>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, W, H, x0, y0, aligned,
-                                  sm.tile);
+        const bool small = load_tile<T, K, NT, true, true>(a.src + (uint64_t)f * a.src_stride, a.src_pitch, W, H,
+                                                           x0, y0, aligned, sm.tile);
+        post_small(sm.large, small);
         if (tid == 0) sm.count = 0;
         __syncthreads();
+        // pass 2 reads pass-1 results, which are values of the staged block, so
+        // the staged values decide both passes' detection path
+        const bool f16 = tile_small<NT>(sm.large);
         const int px = x0 + 4 * tx, py = y0 + strip * R;
         const uint32_t in_frame = box_bits(R, px, py, 0, W, 0, H);
         const uint32_t out = box_bits(R, px, py, ox, min(ox + kFusedTileW, W), oy, min(oy + OH, H));
 
         // pass 1 on every frame pixel of the block
-        const uint32_t f1 = detect_block<K>(sm.tile, strip, tx, a.pk_one) & in_frame;
+        const uint32_t f1 = (f16 ? detect_block<K, true>(sm.tile, strip, tx, a.pk_one)
+                                 : detect_block<K, false>(sm.tile, strip, tx, a.pk_one)) &
+                            in_frame;
         n1 += __builtin_popcount(f1 & out);
         if constexpr (K == 3) {
             // dense 3 x 3 path: the whole block in registers, written back once
@@ -100,7 +106,9 @@ __global__ __launch_bounds__(NT) void fnr_fused2_kernel(StackArgs a) {
 
         // pass 2 on the output pixels
         __builtin_amdgcn_s_setprio(0);
-        const uint32_t f2 = detect_block<K>(sm.tile, strip, tx, a.pk_one) & out;
+        const uint32_t f2 = (f16 ? detect_block<K, true>(sm.tile, strip, tx, a.pk_one)
+                                 : detect_block<K, false>(sm.tile, strip, tx, a.pk_one)) &
+                            out;
         n2 += __builtin_popcount(f2);
         uint32_t o2[R][2];
         if constexpr (K == 3) {

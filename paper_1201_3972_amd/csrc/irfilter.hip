@@ -20,7 +20,7 @@ namespace {
 
 using namespace host;
 
-constexpr int kVersion = (1 << 16) | 1;  // 1.1: pass fusion, windows up to 31x31, directional detector
+constexpr int kVersion = (1 << 16) | 2;  // 1.2: windows up to 63x63 (1.1: pass fusion, directional detector)
 
 // Tuning table of the single-size kernels, per pixel type and window: 0 means
 // the untuned default, otherwise threads | select << 16.  Entries change only
@@ -372,7 +372,7 @@ const char *ir_filter_status_string(irf_status s) {
         case IRF_ERR_DIMS: return "invalid dimensions";
         case IRF_ERR_PITCH: return "pitch or stride too small";
         case IRF_ERR_DTYPE: return "unsupported pixel type";
-        case IRF_ERR_WINDOW: return "window must be odd and within 3..31 (3..15 for batches)";
+        case IRF_ERR_WINDOW: return "window must be odd and within 3..63 (3..31 for batch plans and the server)";
         case IRF_ERR_PASSES: return "invalid pass count or missing scratch";
         case IRF_ERR_ALIAS: return "output overlaps an input";
         case IRF_ERR_HIP: return "HIP error";

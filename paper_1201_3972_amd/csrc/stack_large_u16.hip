@@ -1,9 +1,10 @@
 // stack_large_u16.hip -- the 16-bit instantiations of the single-size kernels
-// for windows 17x17 to 31x31 (group bisection).
+// for windows 17x17 to 31x31 (group bisection and the radix select).
 #include "stack_launch.hpp"
 
 namespace irf {
 bool launch_stack_large_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s) {
-    return stack_impl::launch_stack<uint16_t, true>(window, mode, t, a, s);
+    if (window > kLargeMaxWindow) return launch_stack_huge_u16(window, mode, t, a, s);
+    return stack_impl::launch_stack<uint16_t, stack_impl::kLargeWindows>(window, mode, t, a, s);
 }
 }  // namespace irf

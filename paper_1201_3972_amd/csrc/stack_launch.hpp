@@ -23,21 +23,26 @@ inline Tuning default_tuning(int window) { return {default_threads(window), defa
 
 // Whether a kernel exists for (window, tuning): 128 or 256 threads; networks
 // and one-lane bisection up to 15x15, group bisection and the histogram radix
-// select above.
+// select up to 31x31; above that group bisection on 128 threads only.
 inline bool tuning_available(int window, Tuning t) {
     if (t.threads != 128 && t.threads != 256) return false;
     if (window <= kNetworkMaxWindow) return t.select == kSelectNetwork || t.select == kSelectBisect;
-    return t.select == kSelectGroup || t.select == kSelectHist;
+    if (window <= kLargeMaxWindow) return t.select == kSelectGroup || t.select == kSelectHist;
+    return t.threads == 128 && t.select == kSelectGroup;
 }
 
 // Launch the stack kernel of the pixel type for a.total_tiles tiles; false if
 // the combination has no kernel (nothing is launched then).  Windows above
-// 15x15 go to launch_stack_large_*, instantiated in their own translation
-// units (stack_large_u8.hip, stack_large_u16.hip).
+// 15x15 go to launch_stack_large_*, and those above 31x31 on to
+// launch_stack_huge_*, each instantiated in translation units of their own
+// (stack_large_u8.hip, stack_large_u16.hip, stack_huge_u8.hip,
+// stack_huge_u16.hip) so the build stays parallel.
 bool launch_stack_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
 bool launch_stack_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
 bool launch_stack_large_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
 bool launch_stack_large_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
+bool launch_stack_huge_u8(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
+bool launch_stack_huge_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s);
 
 // Two passes in one launch (fused.hip): windows up to 9x9, workgroups of 256 or
 // 512 threads (blocks of 128 x 64 or 128 x 128 pixels).
@@ -94,9 +99,11 @@ bool launch_threads(int select, const StackArgs &a, hipStream_t s) {
         launch_variant<T, K, MODE, NT, default_select(K)>(a, s);
         return true;
     } else if constexpr (K > kNetworkMaxWindow) {
-        if (select == kSelectHist) {
-            launch_variant<T, K, MODE, NT, kSelectHist>(a, s);
-            return true;
+        if constexpr (K <= kLargeMaxWindow) {
+            if (select == kSelectHist) {
+                launch_variant<T, K, MODE, NT, kSelectHist>(a, s);
+                return true;
+            }
         }
         if (select != kSelectGroup) return false;
         launch_variant<T, K, MODE, NT, kSelectGroup>(a, s);
@@ -119,14 +126,19 @@ bool launch_threads(int select, const StackArgs &a, hipStream_t s) {
 template <typename T, int K, int MODE>
 bool launch_tuned(Tuning t, const StackArgs &a, hipStream_t s) {
     if (t.threads == 128) return launch_threads<T, K, MODE, 128>(t.select, a, s);
-    if (t.threads == 256) return launch_threads<T, K, MODE, 256>(t.select, a, s);
+    if constexpr (K <= kLargeMaxWindow) {
+        if (t.threads == 256) return launch_threads<T, K, MODE, 256>(t.select, a, s);
+    }
     return false;
 }
 
-// LARGE: the windows above 15x15, else those up to it.
-template <typename T, int MODE, bool LARGE>
+// The window ranges of the translation units: up to 15x15, 17x17 .. 31x31,
+// 33x33 .. 63x63.
+enum WindowRange : int { kSmallWindows = 0, kLargeWindows = 1, kHugeWindows = 2 };
+
+template <typename T, int MODE, int RANGE>
 bool launch_window(int window, Tuning t, const StackArgs &a, hipStream_t s) {
-    if constexpr (!LARGE) {
+    if constexpr (RANGE == kSmallWindows) {
         switch (window) {
             case 3: return launch_tuned<T, 3, MODE>(t, a, s);
             case 5: return launch_tuned<T, 5, MODE>(t, a, s);
@@ -137,7 +149,7 @@ bool launch_window(int window, Tuning t, const StackArgs &a, hipStream_t s) {
             case 15: return launch_tuned<T, 15, MODE>(t, a, s);
             default: return false;
         }
-    } else {
+    } else if constexpr (RANGE == kLargeWindows) {
         switch (window) {
             case 17: return launch_tuned<T, 17, MODE>(t, a, s);
             case 19: return launch_tuned<T, 19, MODE>(t, a, s);
@@ -149,18 +161,39 @@ bool launch_window(int window, Tuning t, const StackArgs &a, hipStream_t s) {
             case 31: return launch_tuned<T, 31, MODE>(t, a, s);
             default: return false;
         }
+    } else {
+        switch (window) {
+            case 33: return launch_tuned<T, 33, MODE>(t, a, s);
+            case 35: return launch_tuned<T, 35, MODE>(t, a, s);
+            case 37: return launch_tuned<T, 37, MODE>(t, a, s);
+            case 39: return launch_tuned<T, 39, MODE>(t, a, s);
+            case 41: return launch_tuned<T, 41, MODE>(t, a, s);
+            case 43: return launch_tuned<T, 43, MODE>(t, a, s);
+            case 45: return launch_tuned<T, 45, MODE>(t, a, s);
+            case 47: return launch_tuned<T, 47, MODE>(t, a, s);
+            case 49: return launch_tuned<T, 49, MODE>(t, a, s);
+            case 51: return launch_tuned<T, 51, MODE>(t, a, s);
+            case 53: return launch_tuned<T, 53, MODE>(t, a, s);
+            case 55: return launch_tuned<T, 55, MODE>(t, a, s);
+            case 57: return launch_tuned<T, 57, MODE>(t, a, s);
+            case 59: return launch_tuned<T, 59, MODE>(t, a, s);
+            case 61: return launch_tuned<T, 61, MODE>(t, a, s);
+            case 63: return launch_tuned<T, 63, MODE>(t, a, s);
+            default: return false;
+        }
     }
 }
 
-template <typename T, bool LARGE>
+template <typename T, int RANGE>
 bool launch_stack(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s) {
     switch (mode) {
-        case MODE_DETECT: return launch_window<T, MODE_DETECT, LARGE>(window, t, a, s);
-        case MODE_FNR: return launch_window<T, MODE_FNR, LARGE>(window, t, a, s);
-        case MODE_MEDIAN_MASK: return launch_window<T, MODE_MEDIAN_MASK, LARGE>(window, t, a, s);
-        case MODE_MEDIAN_ALL: return launch_window<T, MODE_MEDIAN_ALL, LARGE>(window, t, a, s);
+        case MODE_DETECT: return launch_window<T, MODE_DETECT, RANGE>(window, t, a, s);
+        case MODE_FNR: return launch_window<T, MODE_FNR, RANGE>(window, t, a, s);
+        case MODE_MEDIAN_MASK: return launch_window<T, MODE_MEDIAN_MASK, RANGE>(window, t, a, s);
+        case MODE_MEDIAN_ALL: return launch_window<T, MODE_MEDIAN_ALL, RANGE>(window, t, a, s);
         case MODE_DETECT_DIR:  // the 3 x 3 directional test only
-            if constexpr (!LARGE) return window == 3 && launch_tuned<T, 3, MODE_DETECT_DIR>(t, a, s);
+            if constexpr (RANGE == kSmallWindows)
+                return window == 3 && launch_tuned<T, 3, MODE_DETECT_DIR>(t, a, s);
             return false;
         default: return false;
     }

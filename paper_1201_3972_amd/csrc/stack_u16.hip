@@ -4,6 +4,6 @@
 namespace irf {
 bool launch_stack_u16(int window, int mode, Tuning t, const StackArgs &a, hipStream_t s) {
     if (window > kNetworkMaxWindow) return launch_stack_large_u16(window, mode, t, a, s);
-    return stack_impl::launch_stack<uint16_t, false>(window, mode, t, a, s);
+    return stack_impl::launch_stack<uint16_t, stack_impl::kSmallWindows>(window, mode, t, a, s);
 }
 }  // namespace irf

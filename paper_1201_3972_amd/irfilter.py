@@ -73,8 +73,8 @@ IRF_SELECT_GROUP = 3
 IRF_SELECT_HIST = 4
 SELECT_NAMES = {IRF_SELECT_NETWORK: "network", IRF_SELECT_BISECT: "bisect", IRF_SELECT_GROUP: "group",
                 IRF_SELECT_HIST: "hist"}
-MAX_WINDOW = 31        # single-size entry points
-MAX_BATCH_WINDOW = 31  # batch plans and the server (every entry point: 3..31)
+MAX_WINDOW = 63        # single-frame and stack entry points
+MAX_BATCH_WINDOW = 31  # batch plans and the server
 
 
 IRF_PLAN_GRAPH = 1

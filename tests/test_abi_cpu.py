@@ -71,8 +71,9 @@ def run(lib, src=SRC, sp=640, dst=DST, dp=640, W=320, H=240, dt=1, k=3, passes=1
     (dict(src=None), -1), (dict(dst=None), -1),
     (dict(W=0), -2), (dict(H=0), -2), (dict(W=-5), -2), (dict(W=32769), -2), (dict(H=40000), -2),
     (dict(dt=0), -4), (dict(dt=3), -4),
-    (dict(k=1), -5), (dict(k=4), -5), (dict(k=32), -5), (dict(k=33), -5), (dict(k=0), -5), (dict(k=-3), -5),
+    (dict(k=1), -5), (dict(k=4), -5), (dict(k=32), -5), (dict(k=65), -5), (dict(k=0), -5), (dict(k=-3), -5),
     (dict(k=31, passes=0), -6),  # 31x31 is a valid window: validation reaches the pass count
+    (dict(k=63, passes=0), -6),  # and so is 63x63
     (dict(passes=0), -6), (dict(passes=17), -6), (dict(passes=2), -6),
     (dict(sp=319), -3), (dict(dt=2, sp=639, dp=640), -3), (dict(dp=100), -3),
     (dict(dst=SRC + 1000), -7),
@@ -118,7 +119,7 @@ def test_median_validation(lib):
     f = lib.ir_filter_median
     assert f(SRC, 640, None, 0, None, 640, 320, 240, 2, 3, None) == -1
     assert f(SRC, 640, MASK, 100, DST, 640, 320, 240, 2, 3, None) == -3
-    assert f(SRC, 640, MASK, 320, DST, 640, 320, 240, 2, 33, None) == -5
+    assert f(SRC, 640, MASK, 320, DST, 640, 320, 240, 2, 65, None) == -5
     assert f(SRC, 640, None, 0, SRC, 640, 320, 240, 2, 3, None) == -7
     assert f(SRC, 640, DST, 320, DST, 640, 320, 240, 2, 3, None) == -7
 

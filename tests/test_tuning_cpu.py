@@ -24,7 +24,7 @@ def lib():
 def _restore_defaults():
     yield
     for dt in ("u8", "u16"):
-        for k in range(3, 32, 2):
+        for k in range(3, 64, 2):
             irfilter.set_tuning(dt, k, 0, 0)
             irfilter.set_fusion(dt, k, -1)
     irfilter.set_batch_threads(0)
@@ -38,6 +38,8 @@ def test_defaults():
             assert irfilter.get_tuning(dt, k) == (256, irfilter.IRF_SELECT_NETWORK)
         for k in range(17, 32, 2):
             assert irfilter.get_tuning(dt, k) == (256, irfilter.IRF_SELECT_GROUP)
+        for k in range(33, 64, 2):
+            assert irfilter.get_tuning(dt, k) == (128, irfilter.IRF_SELECT_GROUP)
     assert irfilter.get_batch_threads() == 128
 
 
@@ -55,7 +57,9 @@ def test_set_get_and_restore():
     (("u16", 5, 128, 3), -11),
     (("u16", 5, 128, 0), -11),
     (("u16", 4, 128, 1), -5),
-    (("u16", 33, 128, 1), -5),
+    (("u16", 65, 128, 1), -5),
+    (("u16", 33, 256, 3), -11),  # above 31x31: 128 threads only
+    (("u16", 33, 128, 4), -11),  # and no radix select
     (("u16", 17, 128, 1), -11),  # no network above 15x15
     (("u16", 17, 128, 2), -11),  # nor one-lane bisection
     (("u16", 5, 128, 3), -11),   # group bisection only above 15x15
@@ -132,7 +136,7 @@ def test_resolve_fusion_follows_the_setting():
 
 @pytest.mark.parametrize("dt,k,threads,status", [
     ("u16", 11, 256, -11), ("u16", 15, 512, -11), ("u16", 5, 128, -11), ("u16", 5, 1, -11),
-    ("u16", 5, -2, -11), ("u16", 4, 256, -5), ("u16", 33, 0, -5), ("u16", 17, 256, -11),
+    ("u16", 5, -2, -11), ("u16", 4, 256, -5), ("u16", 65, 0, -5), ("u16", 17, 256, -11),
 ])
 def test_invalid_fusion(dt, k, threads, status):
     lib = irfilter.load()
@@ -192,6 +196,9 @@ def test_candidates_cover_every_available_kernel():
             irfilter.set_tuning("u8", k, t, s)
             assert irfilter.get_tuning("u8", k) == (t, s)
         irfilter.set_tuning("u8", k, 0, 0)
+    for k in (33, 47, 63):
+        assert autotune.candidates(k) == [(128, irfilter.IRF_SELECT_GROUP)]
+    for k in autotune.LARGE_WINDOWS:
         # networks and one-lane bisection do not exist above 15x15, the radix select not below
         with pytest.raises(irfilter.IrfError):
             irfilter.set_tuning("u8", k, 256, irfilter.IRF_SELECT_NETWORK)

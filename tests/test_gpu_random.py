@@ -1,6 +1,6 @@
 """Seeded random GPU parity cases across the whole surface of the C ABI.
 
-Each case draws a frame shape, pixel type, window (3..31), noise, entry point
+Each case draws a frame shape, pixel type, window (3..63), noise, entry point
 (the whole filter with 1-3 passes, detection, the masked or plain median, the
 directional detector), kernel choices (workgroup size, selection algorithm,
 fusion of passes) and a layout (aligned or offset rows), and checks the result
@@ -20,8 +20,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 N_CASES = 160
-WINDOWS = [3, 5, 7, 9, 11, 13, 15, 17, 21, 25, 31]
-WEIGHTS = [.16, .16, .14, .12, .08, .06, .06, .06, .06, .05, .05]
+WINDOWS = [3, 5, 7, 9, 11, 13, 15, 17, 21, 25, 31, 33, 45, 63]
+WEIGHTS = [.15, .15, .13, .11, .08, .06, .06, .06, .05, .04, .04, .03, .02, .02]
 
 
 def say(msg):
@@ -58,14 +58,17 @@ def draw(case):
     W, H = int(rng.integers(1, 600)), int(rng.integers(1, 300))
     if k >= 17:
         W, H = min(W, 260), min(H, 160)
+    if k >= 33:
+        W, H = min(W, 200), min(H, 120)
     op = str(rng.choice(["run", "run", "run", "detect", "masked", "median", "directional"]))
     passes = int(rng.choice([1, 2, 3], p=[.6, .3, .1])) if op == "run" else 1
     noise = str(rng.choice(["sp", "rv", "mixed", "none"]))
     density = float(rng.uniform(0.05, 0.6))
     seed = int(rng.integers(1 << 30))
     ties = rng.random() < 0.1
-    sels = [irfilter.IRF_SELECT_NETWORK, irfilter.IRF_SELECT_BISECT] if k <= 15 else [irfilter.IRF_SELECT_GROUP]
-    threads, sel = int(rng.choice([128, 256])), int(rng.choice(sels))
+    sels = ([irfilter.IRF_SELECT_NETWORK, irfilter.IRF_SELECT_BISECT] if k <= 15 else
+            [irfilter.IRF_SELECT_GROUP, irfilter.IRF_SELECT_HIST] if k <= 31 else [irfilter.IRF_SELECT_GROUP])
+    threads, sel = int(rng.choice([128, 256] if k <= 31 else [128])), int(rng.choice(sels))
     fusion = int(rng.choice([-1, 0, 256, 512])) if k <= 9 else int(rng.choice([-1, 0]))
     off = int(rng.choice([0, 0, 1, 3]))
     return dict(k=k, dt=dt, W=W, H=H, op=op, passes=passes, noise=noise, density=density, seed=seed, ties=ties,

@@ -455,6 +455,40 @@ def section_c5(torch, serving, oracle, dev, duration: float = 3.0) -> dict:
         del reqs, streams
     out["sustained_at_p99_bound"] = sustained
     out["parity"] = f"all {checked} served results of all runs equal the oracle's ({len(cache)} distinct frame/window pairs)"
+    # the host link the served frames cross: copy commands between pinned host
+    # memory and the device, each direction alone and both at once
+    n = 256 << 20
+    h_in = torch.empty(n, dtype=torch.uint8).pin_memory()
+    h_out = torch.empty(n, dtype=torch.uint8).pin_memory()
+    d_a = torch.empty(n, dtype=torch.uint8, device=dev)
+    d_b = torch.zeros(n, dtype=torch.uint8, device=dev)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def link(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            t1 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t1)
+        return best
+
+    def both():
+        with torch.cuda.stream(s1):
+            d_a.copy_(h_in, non_blocking=True)
+        with torch.cuda.stream(s2):
+            h_out.copy_(d_b, non_blocking=True)
+
+    t_h2d = link(lambda: d_a.copy_(h_in, non_blocking=True))
+    t_d2h = link(lambda: h_out.copy_(d_b, non_blocking=True))
+    t_both = link(both)
+    out["host_link_GBps"] = {"h2d": round(n / t_h2d / 1e9, 1), "d2h": round(n / t_d2h / 1e9, 1),
+                             "both_at_once_total": round(2 * n / t_both / 1e9, 1),
+                             "form": "256 MiB copy commands between pinned host memory and the device"}
+    log(f"c5 host link: {out['host_link_GBps']}")
+    del h_in, h_out, d_a, d_b
     return out
 
 

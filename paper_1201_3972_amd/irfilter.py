@@ -115,8 +115,7 @@ def load(path: Optional[str] = None):
         return _lib
     p = path or LIB_PATH
     if not os.path.exists(p):
-        raise LibraryNotBuilt(f"{p} is missing: run paper_1201_3972_amd.build.build() "
-                              "(or __graft_entry__.build()) first")
+        raise LibraryNotBuilt(f"{p} is missing: run paper_1201_3972_amd.build.build() first")
     lib = ctypes.CDLL(p)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -57,12 +57,39 @@ TRAFFIC_SOURCES = ("paper_1201_3972_amd/csrc/stack_u16.hip", "paper_1201_3972_am
                    "paper_1201_3972_amd/csrc/host_common.hpp", "include/irfilter.h")
 
 
+def code_text(src: str) -> str:
+    """C++ source without its comments, trailing blanks and empty lines: what the
+    compiler sees, so that the record's stamp survives comment edits and only
+    those.  String and character literals are kept as written."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (" ".join(line.split()) for line in "".join(out).split("\n"))
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for name in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, name), "rb") as fh:
+        with open(os.path.join(ROOT, name), encoding="utf-8") as fh:
             h.update(name.encode())
-            h.update(fh.read())
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

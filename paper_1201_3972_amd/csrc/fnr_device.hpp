@@ -1745,8 +1745,9 @@ __device__ __forceinline__ bool tile_small(const uint8_t *large) {
 
 // Occupancy target of the stack kernel: the 5x5 FNR kernel holds six waves per
 // SIMD (its LDS allows six 256-thread workgroups per CU; without the hint its
-// two detection paths take 96 VGPRs and five waves: 2% slower); the others
-// take what their registers and LDS give.
+// two detection paths take 81 VGPRs and five waves, 96 VGPRs before the
+// detection's 64-bit LDS reads, which measured 2% slower); the others take
+// what their registers and LDS give.
 constexpr int stack_waves(int K, int MODE) { return K == 5 && MODE == MODE_FNR ? 6 : 1; }
 
 template <typename T, int K, int MODE, int NT, int SEL>

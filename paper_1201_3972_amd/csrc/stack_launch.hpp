@@ -60,9 +60,12 @@ constexpr int kFusionAuto = -1;
 // 120 x (TH - k + 1) of its 128 x TH pixels, so its tiling never covers fewer
 // pixels than the tiles of two single passes (6 fused tiles cover a 640-pixel
 // row that 5 plain tiles cover, for one); at equal coverage separate passes
-// measured faster at every window 3x3 to 9x9 (320x240 u8 and 640x512 u16
-// stacks).  The fused kernels run when set explicitly, or when the autotuner
-// finds one faster on the caller's frames.
+// measured faster at 3x3 to 7x7 (320x240 u8 and 640x512 u16 stacks).  The
+// exception is 8-bit 9x9, where the 512-thread fused kernel measured 1.22x
+// faster on 320x240 frames and 1.1x on 640x512 ones: that choice is left to
+// the autotuner's table, which takes it from its own measurement.  The fused
+// kernels run when set explicitly, or when the autotuner finds one faster on
+// the caller's frames.
 inline int auto_fusion(int /*width*/, int /*height*/, int /*window*/, int /*plain_threads*/) { return 0; }
 // Launch the fused kernel for a.total_tiles fused tiles (the caller sets the
 // tile counts from kFusedTileW and fused_tile_rows); false if no kernel exists.

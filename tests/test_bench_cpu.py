@@ -77,6 +77,21 @@ def test_ingest_round_trip(tmp_path):
     assert os.path.exists(out)
 
 
+def test_code_text_drops_comments_only():
+    src = ('int a = 1;  // trailing\n'
+           '/* a block\n   over lines */\n'
+           '\n'
+           'const char *s = "// kept", *t = "/* kept */";\n'
+           "char q = '\\'';  int b = 2 /* inline */ + 3;\n")
+    text = bench.code_text(src)
+    assert text == ('int a = 1;\n'
+                    'const char *s = "// kept", *t = "/* kept */";\n'
+                    "char q = '\\''; int b = 2 + 3;")
+    # a comment edit keeps the stamp, a code edit changes it
+    assert bench.code_text(src.replace("trailing", "other words")) == text
+    assert bench.code_text(src.replace("= 2", "= 4")) != text
+
+
 def test_valu_peak():
     # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
     assert bench.VALU_PEAK_T == pytest.approx(39.3216)

@@ -1344,15 +1344,21 @@ struct HistSpace<NT, true> {
     alignas(16) uint32_t bins[NT / kHistLanes][kHistBins];
 };
 
-// Flagged-pixel list of the persistent stack kernel at 5x5: 3/8 of the tile's
-// pixels.  The rare tile with more flagged pixels selects in rounds and stores
-// its medians straight to the frame (median_into_tile), so the list does not
-// need a slot per pixel, and the smaller LDS footprint lets five workgroups
-// share a CU instead of four: 5% faster on the 640x512 stack with 256-thread
-// workgroups.  At 7x7 the same list measured 4% slower (five workgroups of 97
-// VGPRs), and the other windows are held to four waves per SIMD or fewer by
-// their registers, so they keep a slot per pixel.
-constexpr int stack_list(int K, int tile_px) { return K == 5 ? tile_px * 3 / 8 : tile_px; }
+// Flagged-pixel list of the persistent stack kernel at 5x5 and 7x7: 3/8 of the
+// tile's pixels.  The rare tile with more flagged pixels selects in rounds and
+// stores its medians straight to the frame (median_into_tile), so the list
+// does not need a slot per pixel, and the smaller LDS footprint lets more
+// workgroups share a CU: at 5x5 six 256-thread workgroups instead of four (5%
+// faster on the 640x512 stack), at 7x7 five instead of four (5% faster, once
+// the detection's 64-bit LDS reads had brought the kernel to 92 VGPRs; at 97 it
+// had measured 4% slower).  The standard median filter selects every pixel, so
+// every tile takes the rounds: at 5x5 that still measured 5% faster than a
+// slot per pixel, at 7x7 2-4% slower, so there it keeps the full list.  The
+// other windows are held to four waves per SIMD or fewer by their registers,
+// so they keep a slot per pixel.
+constexpr int stack_list(int K, int MODE, int tile_px) {
+    return K == 5 || (K == 7 && MODE != MODE_MEDIAN_ALL) ? tile_px * 3 / 8 : tile_px;
+}
 
 template <int K, int NT = kThreads, int SEL = 0, int LIST = Geometry<K, NT>::tile_px>
 struct TileSmem {
@@ -1757,7 +1763,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stack_waves(
     // the modes that select (K > 3: 3 x 3 computes every median in registers)
     // use the short list; detection has none to speak of
     constexpr bool kSelects = K > 3 && MODE != MODE_DETECT && MODE != MODE_DETECT_DIR;
-    constexpr int LIST = kSelects ? stack_list(K, G::tile_px) : 2;
+    constexpr int LIST = kSelects ? stack_list(K, MODE, G::tile_px) : 2;
     constexpr bool kDetects = MODE == MODE_DETECT || MODE == MODE_FNR;  // min / max detection
     __shared__ __attribute__((aligned(16))) SmemFor<K, NT, SEL, LIST> sm;
     const TileRange rg = xcd_range(blockIdx.x, gridDim.x, a.total_tiles);

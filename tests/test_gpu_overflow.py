@@ -1,6 +1,7 @@
-"""Tiles whose flagged pixels overflow the 5x5 stack kernel's list (more than 3/8
-of the tile): they select in rounds and store every median straight to the
-frame after storing the tile unfiltered.  Frames with flag rates from about
+"""Tiles whose flagged pixels overflow the 5x5 and 7x7 stack kernels' list (more
+than 3/8 of the tile; the 7x7 standard median filter keeps a slot per pixel):
+they select in rounds and store every median straight to the frame after
+storing the tile unfiltered.  Frames with flag rates from about
 a third to all pixels, ragged sizes and both workgroup sizes, against the
 oracle (whole frames, every pixel and the count)."""
 
@@ -85,17 +86,47 @@ def test_dense_flags_plain_median_and_stack(dev, k):
     assert (out[:, :, 270:] == 0x5a5a).all()  # row padding untouched
 
 
+@pytest.mark.parametrize("k", [5, 7])
 @pytest.mark.parametrize("dt", ["u8", "u16"])
-def test_dense_caller_mask(dev, dt):
+def test_dense_caller_mask(dev, dt, k):
     # the masked median with a caller mask that marks about 70 % of the pixels
-    rng = np.random.default_rng(77 + (dt == "u16"))
+    rng = np.random.default_rng(77 + (dt == "u16") + 2 * k)
     hi = 256 if dt == "u8" else 1 << 14
     f = rng.integers(0, hi, size=(150, 261)).astype(np.uint8 if dt == "u8" else np.uint16)
     mask = (rng.random(f.shape) < 0.7).astype(np.uint8)
     src = to_dev(torch, f, dev)
     m = torch.from_numpy(mask).to(dev)
     dst = torch.empty_like(src)
-    say(f"case overflow caller mask {dt} k=5")
-    irfilter.ir_filter_median(src, dst, 5, mask=m)
+    say(f"case overflow caller mask {dt} k={k}")
+    irfilter.ir_filter_median(src, dst, k, mask=m)
     torch.cuda.synchronize()
-    assert np.array_equal(to_host(torch, dst), oracle.median(f, 5, mask)[0])
+    assert np.array_equal(to_host(torch, dst), oracle.median(f, k, mask)[0])
+
+
+@pytest.mark.parametrize("k", [5, 7])
+def test_overflow_stack_and_sparse_neighbours(dev, k):
+    # a stack whose frames alternate between sparse flags (the list holds them)
+    # and dense ones (rounds), with 128 and 256 threads: both paths side by side
+    rng = np.random.default_rng(500 + k)
+    sparse = synth.make_frame(synth.FrameSpec(640, 128, "u16", "rv", 0.3, 20.0, 600 + k))
+    dense = np.where(rng.random((128, 640)) < 0.6, np.where(rng.random((128, 640)) < 0.5, 0, 65535),
+                     sparse).astype(np.uint16)
+    st = np.stack([sparse, dense, sparse, dense])
+    for t in (128, 256):
+        irfilter.set_tuning("u16", k, t, irfilter.IRF_SELECT_NETWORK)
+        try:
+            say(f"case overflow stack k={k} t={t}")
+            src = to_dev(torch, st, dev)
+            dst = torch.empty_like(src)
+            cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+            irfilter.ir_filter_run_frames(src, dst, k, flagged_count=cnt)
+            torch.cuda.synchronize()
+        finally:
+            irfilter.set_tuning("u16", k, 0, 0)
+        out = to_host(torch, dst)
+        tot = 0
+        for i in range(len(st)):
+            want, wc = oracle.fnr(st[i], k)
+            assert np.array_equal(out[i], want), (i, t)
+            tot += int(wc[0])
+        assert int(cnt.item()) == tot

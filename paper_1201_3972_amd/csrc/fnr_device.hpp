@@ -1345,19 +1345,22 @@ struct HistSpace<NT, true> {
 };
 
 // Flagged-pixel list of the persistent stack kernel at 5x5 and 7x7: 3/8 of the
-// tile's pixels.  The rare tile with more flagged pixels selects in rounds and
-// stores its medians straight to the frame (median_into_tile), so the list
-// does not need a slot per pixel, and the smaller LDS footprint lets more
-// workgroups share a CU: at 5x5 six 256-thread workgroups instead of four (5%
-// faster on the 640x512 stack), at 7x7 five instead of four (5% faster, once
-// the detection's 64-bit LDS reads had brought the kernel to 92 VGPRs; at 97 it
-// had measured 4% slower).  The standard median filter selects every pixel, so
-// every tile takes the rounds: at 5x5 that still measured 5% faster than a
-// slot per pixel, at 7x7 2-4% slower, so there it keeps the full list.  The
-// other windows are held to four waves per SIMD or fewer by their registers,
-// so they keep a slot per pixel.
+// tile's pixels at 5x5, a quarter at 7x7.  The rare tile with more flagged
+// pixels selects in rounds and stores its medians straight to the frame
+// (median_into_tile), so the list does not need a slot per pixel, and the
+// smaller LDS footprint lets more workgroups share a CU: six 256-thread
+// workgroups instead of four at both windows (with the occupancy target of
+// stack_waves).  At 5x5 that measured 5% faster on the 640x512 stack; at 7x7
+// five workgroups (a 3/8 list, 92 VGPRs) measured 5% faster and six (a quarter
+// list, 80 VGPRs) 4-5% faster again, and 1.3% faster on 1080p frames with 20%
+// flagged, where some tiles overflow.  (At 97 VGPRs, before the detection's
+// 64-bit LDS reads, the 3/8 list had measured 4% slower at 7x7.)  The standard
+// median filter selects every pixel, so every tile takes the rounds: at 5x5
+// that still measured 5% faster than a slot per pixel, at 7x7 2-4% slower, so
+// there it keeps the full list.  The other windows are held to four waves per
+// SIMD or fewer by their registers, so they keep a slot per pixel.
 constexpr int stack_list(int K, int MODE, int tile_px) {
-    return K == 5 || (K == 7 && MODE != MODE_MEDIAN_ALL) ? tile_px * 3 / 8 : tile_px;
+    return K == 5 ? tile_px * 3 / 8 : K == 7 && MODE != MODE_MEDIAN_ALL ? tile_px / 4 : tile_px;
 }
 
 template <int K, int NT = kThreads, int SEL = 0, int LIST = Geometry<K, NT>::tile_px>
@@ -1749,12 +1752,14 @@ __device__ __forceinline__ bool tile_small(const uint8_t *large) {
     return __builtin_amdgcn_readfirstlane((uint32_t)(any | (any >> 32))) == 0;
 }
 
-// Occupancy target of the stack kernel: the 5x5 FNR kernel holds six waves per
-// SIMD (its LDS allows six 256-thread workgroups per CU; without the hint its
-// two detection paths take 81 VGPRs and five waves, 96 VGPRs before the
-// detection's 64-bit LDS reads, which measured 2% slower); the others take
-// what their registers and LDS give.
-constexpr int stack_waves(int K, int MODE) { return K == 5 && MODE == MODE_FNR ? 6 : 1; }
+// Occupancy target of the stack kernel: the 5x5 and 7x7 FNR kernels hold six
+// waves per SIMD, as their LDS allows six 256-thread workgroups per CU with the
+// short lists of stack_list.  Without the hint the 5x5 kernel's two detection
+// paths take 81 VGPRs and five waves (96 VGPRs before the detection's 64-bit
+// LDS reads, which measured 2% slower), the 7x7 kernel 92 VGPRs and five waves
+// (with the hint: 80 VGPRs, one of them spilled; 4-5% faster); the others
+// take what their registers and LDS give.
+constexpr int stack_waves(int K, int MODE) { return (K == 5 || K == 7) && MODE == MODE_FNR ? 6 : 1; }
 
 template <typename T, int K, int MODE, int NT, int SEL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stack_waves(K, MODE)))) void fnr_persistent_kernel(

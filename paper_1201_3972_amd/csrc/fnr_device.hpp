@@ -1752,17 +1752,24 @@ __device__ __forceinline__ bool tile_small(const uint8_t *large) {
     return __builtin_amdgcn_readfirstlane((uint32_t)(any | (any >> 32))) == 0;
 }
 
-// Occupancy target of the stack kernel: the 5x5 and 7x7 FNR kernels hold six
-// waves per SIMD, as their LDS allows six 256-thread workgroups per CU with the
-// short lists of stack_list.  Without the hint the 5x5 kernel's two detection
-// paths take 81 VGPRs and five waves (96 VGPRs before the detection's 64-bit
-// LDS reads, which measured 2% slower), the 7x7 kernel 92 VGPRs and five waves
-// (with the hint: 80 VGPRs, one of them spilled; 4-5% faster); the others
-// take what their registers and LDS give.
-constexpr int stack_waves(int K, int MODE) { return (K == 5 || K == 7) && MODE == MODE_FNR ? 6 : 1; }
+// Occupancy target of the stack kernel (waves per SIMD; 1 = none).  The 5x5
+// FNR kernels and the 256-thread 7x7 one hold six, as their LDS allows six
+// workgroups of 256 threads per CU with the short lists of stack_list; the
+// 256-thread 11x11 FNR kernel holds four, as its LDS allows four.  Without the
+// target the 5x5 kernel's two detection paths take 81 VGPRs and five waves (96
+// VGPRs before the detection's 64-bit LDS reads, which measured 2% slower),
+// the 7x7 kernel 92 VGPRs and five waves (with it: 80 VGPRs, one spilled; 3-5%
+// faster), the 11x11 kernel 135 VGPRs and three waves (with it: 128 VGPRs,
+// three spilled; 2.3% faster on 1080p frames with 20% flagged, 14% on the
+// 640x512 stack).  The 128-thread 7x7 and 11x11 kernels measured 7-13% slower
+// with the target and run without it; the others take what their registers
+// and LDS give.
+constexpr int stack_waves(int K, int MODE, int NT) {
+    return MODE != MODE_FNR ? 1 : K == 5 ? 6 : K == 7 && NT == 256 ? 6 : K == 11 && NT == 256 ? 4 : 1;
+}
 
 template <typename T, int K, int MODE, int NT, int SEL>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stack_waves(K, MODE)))) void fnr_persistent_kernel(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stack_waves(K, MODE, NT)))) void fnr_persistent_kernel(
     StackArgs a) {
     using G = Geometry<K, NT>;
     // the modes that select (K > 3: 3 x 3 computes every median in registers)

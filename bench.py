@@ -762,6 +762,63 @@ def section_f4(torch, irfilter, synth, oracle, dev) -> dict:
     return out
 
 
+def section_mf(torch, irfilter, synth, oracle, dev, frames: int = 8, reps: int = 20) -> dict:
+    """The standard median filter (every pixel replaced by its window median, the
+    filter the paper compares FNR with), at 3x3, 5x5 and 7x7, over one 1920 x
+    8640 u16 image: eight frames of the 1080p recipe stacked, one launch per
+    window.  FNR over the same image is timed beside it.  Every output pixel is
+    checked against the oracle first, which runs on row bands of the image with
+    r rows of context on each side (exact: no kept row's window reaches a band
+    edge that is not an image edge).  The launches are timed after a quarter
+    second of untimed ones (the oracle pass leaves the device idle)."""
+    with cf.ThreadPoolExecutor(max_workers=_threads()) as ex:
+        pool = list(ex.map(lambda j: synth.make_frame(synth.c3_spec(j)), range(frames)))
+    img = np.ascontiguousarray(np.concatenate(pool, axis=0))
+    H, W = img.shape
+    band = pool[0].shape[0]
+    src = to_dev(torch, img, dev)
+    dst = torch.empty_like(src)
+    windows = (3, 5, 7)
+
+    def banded(fn, k):
+        r = k // 2
+
+        def job(b0):
+            lo, hi = max(0, b0 - r), min(H, b0 + band + r)
+            return fn(img[lo:hi], k)[b0 - lo:b0 - lo + min(band, H - b0)]
+        with cf.ThreadPoolExecutor(max_workers=_threads()) as ex:
+            return np.concatenate(list(ex.map(job, range(0, H, band))), axis=0)
+
+    forms = {"median_filter": (lambda f, k: oracle.median(f, k)[0],
+                               lambda k: irfilter.ir_filter_median(src, dst, k)),
+             "fnr": (lambda f, k: oracle.fnr(f, k)[0], lambda k: irfilter.ir_filter_run(src, dst, k))}
+    for name, (ref, run) in forms.items():
+        for k in windows:
+            run(k)
+            torch.cuda.synchronize()
+            if not dev_equal(torch, dst, banded(ref, k), dev):
+                raise RuntimeError(f"mf section parity failure: {name} at window {k}")
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.25:
+        for _ in range(20):
+            irfilter.ir_filter_median(src, dst, 5)
+        torch.cuda.synchronize()
+    px = H * W
+    out = {"workload": f"one {W}x{H} u16 image ({frames} frames of the 1080p recipe stacked: 14-bit, read noise "
+                       "sigma 20, 40% mixed impulses), one launch per window",
+           "parity": "every output pixel of both forms at every window equals the oracle's", "windows": {}}
+    for k in windows:
+        ent = {}
+        for name, (_, run) in forms.items():
+            ms = _timed(torch, lambda: run(k), reps)
+            ent[name] = {"ms": round(ms, 4), "MP_per_s": round(px / ms / 1e3, 1),
+                         "algorithmic_GBps": round(4 * px / ms / 1e6, 1)}
+        ent["median_filter_over_fnr_time"] = round(ent["median_filter"]["ms"] / ent["fnr"]["ms"], 2)
+        out["windows"][str(k)] = ent
+        log(f"mf {k}x{k}: {ent}")
+    return out
+
+
 def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
     sections = {}
     wanted = [x for x in args.sections.split(",") if x and x != "none"]
@@ -784,6 +841,8 @@ def run_sections(args, torch, irfilter, synth, oracle, dev) -> dict:
             sections["f4_directional_detector"] = section_f4(torch, irfilter, synth, oracle, dev)
         elif name == "f3":
             sections["f3_table1_analogue"] = section_f3(torch, irfilter, synth, oracle, dev)
+        elif name == "mf":
+            sections["mf_median_filter"] = section_mf(torch, irfilter, synth, oracle, dev)
         log(f"section {name}: {time.perf_counter() - t1:.1f}s")
     return sections
 
@@ -800,7 +859,7 @@ def main() -> int:
     ap.add_argument("--no-per-frame", action="store_true", help="skip the per-frame launch baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--sections", default="c1,c3,c4,c5,f1,f2,f3,f4",
+    ap.add_argument("--sections", default="c1,c3,c4,c5,f1,f2,f3,f4,mf",
                     help="extra workloads reported beside the headline (comma list, or 'none')")
     ap.add_argument("--no-headline", action="store_true",
                     help="run only the --sections workloads (for profiling them) and print their JSON")

@@ -1352,15 +1352,14 @@ struct HistSpace<NT, true> {
 // workgroups instead of four at both windows (with the occupancy target of
 // stack_waves).  At 5x5 that measured 5% faster on the 640x512 stack; at 7x7
 // five workgroups (a 3/8 list, 92 VGPRs) measured 5% faster and six (a quarter
-// list, 80 VGPRs) 4-5% faster again, and 1.3% faster on 1080p frames with 20%
+// list, 80 VGPRs) 3-5% faster again, and 1.3% faster on 1080p frames with 20%
 // flagged, where some tiles overflow.  (At 97 VGPRs, before the detection's
 // 64-bit LDS reads, the 3/8 list had measured 4% slower at 7x7.)  The standard
-// median filter selects every pixel, so every tile takes the rounds: at 5x5
-// that still measured 5% faster than a slot per pixel, at 7x7 2-4% slower, so
-// there it keeps the full list.  The other windows are held to four waves per
-// SIMD or fewer by their registers, so they keep a slot per pixel.
-constexpr int stack_list(int K, int MODE, int tile_px) {
-    return K == 5 ? tile_px * 3 / 8 : K == 7 && MODE != MODE_MEDIAN_ALL ? tile_px / 4 : tile_px;
+// median filter selects every pixel; at 5x5 and 7x7 it takes the dense path
+// (dense_block) and needs no list.  The other windows are held to four waves
+// per SIMD or fewer by their registers, so they keep a slot per pixel.
+constexpr int stack_list(int K, int tile_px) {
+    return K == 5 ? tile_px * 3 / 8 : K == 7 ? tile_px / 4 : tile_px;
 }
 
 template <int K, int NT = kThreads, int SEL = 0, int LIST = Geometry<K, NT>::tile_px>
@@ -1463,6 +1462,115 @@ __device__ __forceinline__ void dense3_block(const uint16_t *tile, int strip, in
                             ((uint32_t)__builtin_amdgcn_sbfe(flags, q + 24, 1) & 0xffff0000u);
         out[q][0] = (m0 & s0) | (B[q + 1] & ~s0);
         out[q][1] = (m1 & s1) | (D[q + 1] & ~s1);
+    }
+}
+
+// The standard median filter at 5 x 5 and 7 x 7 takes a dense path too: every
+// pixel is selected, and computing all medians of the thread's block from
+// sorted window columns costs less than compacting the whole tile.  Per output
+// row, the K + 2 column-pair streams P_c = (column c, column c+1), c = -r..r+2,
+// of the K window rows are each sorted (packed: one sort serves two
+// neighbouring columns), and the K sorted columns of a window are merged in
+// the manner of forgetful selection (Fold): whenever the run of merged values
+// holds values that cannot be the median whatever the columns not yet merged
+// hold, they are dropped.  The K - 2 columns that both output pairs of the
+// thread share (P_-r+2 .. P_r) are merged once; each pair then merges its own
+// two columns, which leaves one value, its median.
+
+// One forgetful merge step: a sorted run of L values, in which the median has
+// rank T, takes a sorted column of S values, with U values (this column
+// included) not yet merged.  Of the L + S merged values the `low` smallest lie
+// below the median even if every value still unmerged were smaller, and the
+// `high` largest lie above it: both are dropped, leaving `keep` values in which
+// the median has rank `rank`.
+template <int L, int S, int T, int U>
+struct Fold {
+    static constexpr int M = L + S, left = U - S;
+    static constexpr int low = T > left ? T - left : 0;
+    static constexpr int high = M - 1 > T ? M - 1 - T : 0;
+    static constexpr int keep = M - low - high, rank = T - low;
+};
+
+template <int L, int S, int T, int U>
+__device__ __forceinline__ void fold_in(const uint32_t *run, const uint32_t *col, uint32_t *out) {
+    using F = Fold<L, S, T, U>;
+    uint32_t m[F::M];
+    merge_sorted<L, S>(run, col, m);
+#pragma unroll
+    for (int i = 0; i < F::keep; ++i) out[i] = m[F::low + i];
+}
+
+// Fold columns J .. JEND-1 of col (each of K sorted values) into a run.
+template <int K, int J, int JEND, int L, int T, int U>
+struct FoldColumns {
+    using F = Fold<L, K, T, U>;
+    using Next = FoldColumns<K, J + 1, JEND, F::keep, F::rank, F::left>;
+    static constexpr int keep = Next::keep, rank = Next::rank, left = Next::left;
+    template <int NS>
+    __device__ static void run(const uint32_t *r, const uint32_t (&col)[NS][K], uint32_t *out) {
+        uint32_t m[F::keep];
+        fold_in<L, K, T, U>(r, col[J], m);
+        Next::run(m, col, out);
+    }
+};
+template <int K, int JEND, int L, int T, int U>
+struct FoldColumns<K, JEND, JEND, L, T, U> {
+    static constexpr int keep = L, rank = T, left = U;
+    template <int NS>
+    __device__ static void run(const uint32_t *r, const uint32_t (&)[NS][K], uint32_t *out) {
+#pragma unroll
+        for (int i = 0; i < L; ++i) out[i] = r[i];
+    }
+};
+
+// Output pairs of the thread's 4 x R block at K x K (5 or 7), as dense3_block:
+// the window median where the flag bit is set and the centre otherwise.
+template <int K, int R>
+__device__ __forceinline__ void dense_block(const uint16_t *tile, int strip, int tx, uint32_t flags,
+                                            uint32_t (&out)[R][2]) {
+    static_assert(K == 5 || K == 7, "dense medians from sorted columns at 5 x 5 and 7 x 7");
+    using G = Geometry<K>;
+    constexpr int r = K / 2, NS = K + 2, N = K * K;
+    // the shared columns 2 .. K-1, starting from column 2 alone
+    using Shared = FoldColumns<K, 3, K, K, N / 2, N - K>;
+    using Own1 = Fold<Shared::keep, K, Shared::rank, Shared::left>;
+    using Own2 = Fold<Own1::keep, K, Own1::rank, Own1::left>;
+    static_assert(Own2::keep == 1 && Own2::left == 0, "the fold must end with the median alone");
+    const uint16_t *base = tile + strip * R * G::pitch + G::halo + 4 * tx;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        uint32_t col[NS][K];  // col[j]: stream P_(j-r) over the window rows q..q+K-1
+        uint32_t c0 = 0, c1 = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const uint2 *w = reinterpret_cast<const uint2 *>(base + (q + i) * G::pitch);
+            const uint2 w0 = w[-1], w1 = w[0], w2 = w[1];  // columns -4..-1, 0..3, 4..7
+            const uint32_t d[6] = {w0.x, w0.y, w1.x, w1.y, w2.x, w2.y};  // d[e + 2]: columns (2e, 2e+1)
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                const int c = j - r;
+                col[j][i] = (c & 1) ? shift_pair(d[(c + 1) / 2 + 2], d[(c - 1) / 2 + 2]) : d[c / 2 + 2];
+            }
+            if (i == r) {
+                c0 = w1.x;
+                c1 = w1.y;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NS; ++j) sort_block<K>(col[j]);
+        uint32_t core[Shared::keep];
+        Shared::run(col[2], col, core);
+        uint32_t a[Own1::keep], m0, m1;
+        fold_in<Shared::keep, K, Shared::rank, Shared::left>(core, col[0], a);  // columns (0, 1)
+        fold_in<Own1::keep, K, Own1::rank, Own1::left>(a, col[1], &m0);
+        fold_in<Shared::keep, K, Shared::rank, Shared::left>(core, col[K], a);  // columns (2, 3)
+        fold_in<Own1::keep, K, Own1::rank, Own1::left>(a, col[K + 1], &m1);
+        const uint32_t s0 = ((uint32_t)__builtin_amdgcn_sbfe(flags, q, 1) & 0xffffu) |
+                            ((uint32_t)__builtin_amdgcn_sbfe(flags, q + 16, 1) & 0xffff0000u);
+        const uint32_t s1 = ((uint32_t)__builtin_amdgcn_sbfe(flags, q + 8, 1) & 0xffffu) |
+                            ((uint32_t)__builtin_amdgcn_sbfe(flags, q + 24, 1) & 0xffff0000u);
+        out[q][0] = (m0 & s0) | (c0 & ~s0);
+        out[q][1] = (m1 & s1) | (c1 & ~s1);
     }
 }
 
@@ -1671,11 +1779,15 @@ __device__ __forceinline__ uint32_t process_tile(const StackArgs &a, int tile, S
             }
         }
         return wave_total;
-    } else if constexpr (K == 3) {
-        // dense 3 x 3 path: every pixel's median in registers, kept where flagged
+    } else if constexpr (K == 3 || ((K == 5 || K == 7) && MODE == MODE_MEDIAN_ALL)) {
+        // dense paths (3 x 3, and the 5 x 5 and 7 x 7 median filter): every
+        // pixel's median in registers, kept where flagged
         const uint32_t wave_total = __builtin_amdgcn_readlane(wave_inclusive_sum(__builtin_popcount(flags)), 63);
         uint32_t out[R][2];
-        dense3_block<R>(sm.tile, strip, tx, flags, out);
+        if constexpr (K == 3)
+            dense3_block<R>(sm.tile, strip, tx, flags, out);
+        else
+            dense_block<K, R>(sm.tile, strip, tx, flags, out);
         if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
         uint8_t *dst = a.dst + (uint64_t)f * a.dst_stride;
         const bool full = aligned && x0 + kTileW <= W && y0 + G::TH <= H;  // uniform
@@ -1772,10 +1884,12 @@ template <typename T, int K, int MODE, int NT, int SEL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(stack_waves(K, MODE, NT)))) void fnr_persistent_kernel(
     StackArgs a) {
     using G = Geometry<K, NT>;
-    // the modes that select (K > 3: 3 x 3 computes every median in registers)
+    // the modes that select (K > 3: 3 x 3, and the 5 x 5 and 7 x 7 median filter,
+    // compute every median in registers)
     // use the short list; detection has none to speak of
-    constexpr bool kSelects = K > 3 && MODE != MODE_DETECT && MODE != MODE_DETECT_DIR;
-    constexpr int LIST = kSelects ? stack_list(K, MODE, G::tile_px) : 2;
+    constexpr bool kSelects =
+        K > 3 && MODE != MODE_DETECT && MODE != MODE_DETECT_DIR && !((K == 5 || K == 7) && MODE == MODE_MEDIAN_ALL);
+    constexpr int LIST = kSelects ? stack_list(K, G::tile_px) : 2;
     constexpr bool kDetects = MODE == MODE_DETECT || MODE == MODE_FNR;  // min / max detection
     __shared__ __attribute__((aligned(16))) SmemFor<K, NT, SEL, LIST> sm;
     const TileRange rg = xcd_range(blockIdx.x, gridDim.x, a.total_tiles);

@@ -1868,8 +1868,8 @@ __device__ __forceinline__ bool tile_small(const uint8_t *large) {
 // FNR kernels and the 256-thread 7x7 one hold six, as their LDS allows six
 // workgroups of 256 threads per CU with the short lists of stack_list; the
 // 256-thread 11x11 FNR kernel holds four, as its LDS allows four.  Without the
-// target the 5x5 kernel's two detection paths take 81 VGPRs and five waves (96
-// VGPRs before the detection's 64-bit LDS reads, which measured 2% slower),
+// target the 5x5 kernel's two detection paths take 81 VGPRs and five waves,
+// which measured 2% slower (96 VGPRs before the detection's 64-bit LDS reads),
 // the 7x7 kernel 92 VGPRs and five waves (with it: 80 VGPRs, one spilled; 3-5%
 // faster), the 11x11 kernel 135 VGPRs and three waves (with it: 128 VGPRs,
 // three spilled; 2.3% faster on 1080p frames with 20% flagged, 14% on the
